@@ -1,0 +1,320 @@
+"""Plain FP64 CPU oracle for Nesterov-accelerated ADMM diffeomorphic registration.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this module.  The product path (the
+HIP library and its Python binding) never imports, links or calls it, and it
+shares no code, tables or constants with that path.
+
+Everything here follows the paper (Thorley et al., "Nesterov Accelerated ADMM
+for Fast Diffeomorphic Image Registration") step by step, in NumPy float64,
+with no blocking, fusion or reordering beyond what the paper states:
+
+* Sec. 2, Eq. (1) with N = 1: the deformation is the composition of the
+  per-warping velocity fields, and the *original* source image is warped by
+  the whole composition each time (Sec. 2, the iterative scheme).
+* Sec. 2, Eq. (2) with s = 2: the linearised data term
+  rho(v) = <grad I1, v> + I1 - I0 and the order-n regulariser.
+* Sec. 3, Eq. (3)-(5): variable splitting w = v, scaled augmented Lagrangian
+  and the Nesterov-accelerated ADMM recurrence, including the alpha/gamma
+  momentum scalars and the zero initialisation.
+* Sec. 3, Eq. (6): the closed-form v-step (Sherman-Morrison, s = 2) and the
+  Fourier-diagonalised w-step with the finite-difference symbol of the
+  Laplacian.
+
+Readings of points the paper leaves open (each is listed in the design notes):
+
+* The w-step is read with theta in the numerator,
+  w = F^-1( theta F(v + b_hat) / (theta + lambda F(Delta^n)) ): that is the
+  optimality condition of the w-subproblem of Eq. (5); the printed Eq. (6)
+  omits the factor.
+* F(Delta^n) is the (non-negative) symbol of (-Delta_h)^n for the 7-point
+  periodic Laplacian with unit spacing, as printed in Sec. 3.
+* grad I1 is the periodic central difference (unit spacing) of the warped
+  source image passed to the model (Sec. 2).
+* Warps and compositions use periodic trilinear interpolation (floor of the
+  sample position, indices taken modulo the size).
+* Each warping starts the ADMM loop from zero with alpha^0 = 1 (Sec. 3, text
+  after Eq. (5)); the warping's velocity is the final w iterate.
+* Loop counts are fixed (Sec. 4, first hyperparameter version caps them).
+
+Array conventions: scalar volumes have shape (nz, ny, nx) with x fastest;
+vector fields have shape (3, nz, ny, nx) with component 0 the x displacement,
+1 the y and 2 the z displacement, in voxel units.  Displacements are
+backward (pull): the warped image is I(x + u(x)).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+AXIS_OF_COMPONENT = (2, 1, 0)  # numpy axis that carries x, y, z
+
+
+# ---------------------------------------------------------------------------
+# Nesterov scalars -- Sec. 3, Eq. (5)
+# ---------------------------------------------------------------------------
+def nesterov_alphas(iters: int) -> np.ndarray:
+    """alpha^0 .. alpha^iters of Eq. (5): alpha^0 = 1 and
+    alpha^{k+1} = (1 + sqrt(1 + 4 (alpha^k)^2)) / 2."""
+    a = np.empty(iters + 1, dtype=np.float64)
+    a[0] = 1.0
+    for k in range(iters):
+        a[k + 1] = (1.0 + math.sqrt(1.0 + 4.0 * a[k] * a[k])) / 2.0
+    return a
+
+
+def nesterov_gammas(iters: int) -> np.ndarray:
+    """gamma_k = (alpha^k - 1) / alpha^{k+1}, the extrapolation weight that
+    builds w_hat^{k+1}, b_hat^{k+1} from iterates k and k-1 (Eq. (5))."""
+    a = nesterov_alphas(iters)
+    return (a[:-1] - 1.0) / a[1:]
+
+
+# ---------------------------------------------------------------------------
+# Finite differences and the Laplacian symbol -- Sec. 3, text after Eq. (6)
+# ---------------------------------------------------------------------------
+def central_diff(f: np.ndarray, axis: int) -> np.ndarray:
+    """Periodic central difference with unit spacing along a numpy axis."""
+    return (np.roll(f, -1, axis=axis) - np.roll(f, 1, axis=axis)) / 2.0
+
+
+def gradient(f: np.ndarray) -> np.ndarray:
+    """(d/dx, d/dy, d/dz) of a scalar volume, periodic central differences."""
+    return np.stack([central_diff(f, ax) for ax in AXIS_OF_COMPONENT])
+
+
+def laplacian_symbol(dims_xyz, half: bool = True) -> np.ndarray:
+    """2 (3 - cos(2 pi p/M) - cos(2 pi q/N) - cos(2 pi r/H)) on the DFT grid,
+    i.e. the eigenvalues of the periodic 7-point -Delta_h (Sec. 3).
+
+    Returned with shape (nz, ny, nx//2+1) when ``half`` (the real-FFT half
+    grid of numpy.fft.rfftn over axes (0, 1, 2)), else (nz, ny, nx)."""
+    nx, ny, nz = dims_xyz
+    px = np.arange(nx // 2 + 1 if half else nx)
+    q = np.arange(ny)
+    r = np.arange(nz)
+    cx = np.cos(2.0 * np.pi * px / nx)[None, None, :]
+    cy = np.cos(2.0 * np.pi * q / ny)[None, :, None]
+    cz = np.cos(2.0 * np.pi * r / nz)[:, None, None]
+    return 2.0 * (3.0 - cx - cy - cz)
+
+
+def w_step_multiplier(dims_xyz, lam: float, theta: float, order: int,
+                      half: bool = True) -> np.ndarray:
+    """theta / (theta + lambda * F(Delta^n)) with F(Delta^n) = symbol**n."""
+    k = laplacian_symbol(dims_xyz, half=half) ** order
+    return theta / (theta + lam * k)
+
+
+def fourier_solve(s: np.ndarray, mult: np.ndarray) -> np.ndarray:
+    """w = F^-1( mult * F(s) ) per component (w-step of Eq. (6)).
+
+    F is the unnormalised forward DFT, F^-1 its inverse (numpy convention)."""
+    shape = s.shape[-3:]
+    out = np.empty_like(s)
+    for c in range(s.shape[0]):
+        out[c] = np.fft.irfftn(mult * np.fft.rfftn(s[c], axes=(0, 1, 2)), s=shape, axes=(0, 1, 2))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Periodic trilinear resampling -- Sec. 2 (warping I1 by Id + v)
+# ---------------------------------------------------------------------------
+def trilinear_periodic(f: np.ndarray, disp: np.ndarray) -> np.ndarray:
+    """Sample f at x + disp(x) for every voxel x, trilinear, periodic.
+
+    f: (nz, ny, nx) scalar, or (C, nz, ny, nx) stacked scalars sampled at the
+    same points.  disp: (3, nz, ny, nx) in voxels (component 0 = x)."""
+    nz, ny, nx = disp.shape[1:]
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx),
+                             indexing="ij")
+    px = xx + disp[0]
+    py = yy + disp[1]
+    pz = zz + disp[2]
+    fx = np.floor(px)
+    fy = np.floor(py)
+    fz = np.floor(pz)
+    tx = px - fx
+    ty = py - fy
+    tz = pz - fz
+    ix0 = np.mod(fx.astype(np.int64), nx)
+    iy0 = np.mod(fy.astype(np.int64), ny)
+    iz0 = np.mod(fz.astype(np.int64), nz)
+    ix1 = np.mod(ix0 + 1, nx)
+    iy1 = np.mod(iy0 + 1, ny)
+    iz1 = np.mod(iz0 + 1, nz)
+
+    def one(g):
+        return ((1 - tz) * ((1 - ty) * ((1 - tx) * g[iz0, iy0, ix0] + tx * g[iz0, iy0, ix1])
+                            + ty * ((1 - tx) * g[iz0, iy1, ix0] + tx * g[iz0, iy1, ix1]))
+                + tz * ((1 - ty) * ((1 - tx) * g[iz1, iy0, ix0] + tx * g[iz1, iy0, ix1])
+                        + ty * ((1 - tx) * g[iz1, iy1, ix0] + tx * g[iz1, iy1, ix1])))
+
+    if f.ndim == 3:
+        return one(f)
+    return np.stack([one(f[c]) for c in range(f.shape[0])])
+
+
+def compose(u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Displacement of (Id + u) o (Id + v):  v(x) + u(x + v(x))  (Eq. (1))."""
+    return v + trilinear_periodic(u, v)
+
+
+def expmap(vel: np.ndarray, steps: int) -> np.ndarray:
+    """Scaling and squaring of a stationary velocity field: u = vel / 2^K,
+    then K self-compositions u <- u + u(x + u(x))."""
+    u = vel / float(2 ** steps)
+    for _ in range(steps):
+        u = compose(u, u)
+    return u
+
+
+# ---------------------------------------------------------------------------
+# Data term and the closed-form v-step -- Sec. 2 Eq. (2), Sec. 3 Eq. (6)
+# ---------------------------------------------------------------------------
+def warp_grad_residual(moving: np.ndarray, fixed: np.ndarray, disp: np.ndarray):
+    """I1^w = I1 o (Id + disp);  J = grad I1^w;  r = I1^w - I0.
+
+    The linearised residual of Eq. (2) is then rho(v) = <J, v> + r."""
+    warped = trilinear_periodic(moving, disp)
+    return warped, gradient(warped), warped - fixed
+
+
+def v_step_l2(a: np.ndarray, J: np.ndarray, r: np.ndarray, theta: float) -> np.ndarray:
+    """Solve (J J^T + theta I) v = theta a - J r per voxel (Eq. (6), s = 2),
+    with a = w_hat - b_hat.  By Sherman-Morrison for the rank-one J J^T:
+    v = a - J (J.a + r) / (theta + |J|^2)."""
+    ja = np.sum(J * a, axis=0)
+    jj = np.sum(J * J, axis=0)
+    return a - J * ((ja + r) / (theta + jj))[None]
+
+
+def v_step_l1(a: np.ndarray, J: np.ndarray, r: np.ndarray, theta: float,
+              eps: float = 1e-8) -> np.ndarray:
+    """Eq. (6), s = 1: v = a - z_hat / max(|z_hat|, 1) * J / theta with
+    z_hat = theta rho(a) / (|J|^2 + eps)."""
+    rho = np.sum(J * a, axis=0) + r
+    z = theta * rho / (np.sum(J * J, axis=0) + eps)
+    return a - (z / np.maximum(np.abs(z), 1.0))[None] * J / theta
+
+
+# ---------------------------------------------------------------------------
+# Nesterov-accelerated ADMM -- Sec. 3, Eq. (5) and (6)
+# ---------------------------------------------------------------------------
+@dataclass
+class AdmmResult:
+    w: np.ndarray
+    b: np.ndarray
+    v: np.ndarray
+    gammas: np.ndarray
+    history: list = field(default_factory=list)
+
+
+def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
+         iters: int, data_term: int = 2, eps: float = 1e-8,
+         history: bool = False, mult: np.ndarray | None = None) -> AdmmResult:
+    """Run ``iters`` iterations (k = 0 .. iters-1) of Eq. (5) from the
+    initialisation w_hat^0 = b_hat^0 = 0, alpha^0 = 1.
+
+    Per iteration, in the paper's order:
+      v^k = argmin of the data subproblem          (Eq. (6), top/middle)
+      w^k = F^-1( theta F(v^k + b_hat^k) / (theta + lambda F(Delta^n)) )
+      b^k = b_hat^k + v^k - w^k
+      alpha^{k+1} = (1 + sqrt(1 + 4 (alpha^k)^2)) / 2
+      w_hat^{k+1} = w^k + (alpha^k - 1)/alpha^{k+1} (w^k - w^{k-1})
+      b_hat^{k+1} = b^k + (alpha^k - 1)/alpha^{k+1} (b^k - b^{k-1})
+    ``mult`` overrides the w-step multiplier (used only by tests that plant a
+    mistake to show the pins catch it)."""
+    dims_xyz = (J.shape[3], J.shape[2], J.shape[1])
+    if mult is None:
+        mult = w_step_multiplier(dims_xyz, lam, theta, order)
+    zeros = np.zeros_like(J)
+    w_hat, b_hat = zeros.copy(), zeros.copy()
+    w_prev, b_prev = zeros.copy(), zeros.copy()  # w^{-1}, b^{-1}
+    alpha = 1.0
+    gam = []
+    hist = []
+    w = b = v = zeros
+    for k in range(iters):
+        a = w_hat - b_hat
+        if data_term == 2:
+            v = v_step_l2(a, J, r, theta)
+        else:
+            v = v_step_l1(a, J, r, theta, eps)
+        w = fourier_solve(v + b_hat, mult)
+        b = b_hat + v - w
+        alpha_next = (1.0 + math.sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0
+        g = (alpha - 1.0) / alpha_next
+        gam.append(g)
+        if history:
+            # primal residual |w^k - v^k| and dual residual theta |w^k - w^{k-1}|
+            hist.append({"v": v.copy(), "w": w.copy(), "b": b.copy(),
+                         "primal": float(np.sqrt(np.sum((w - v) ** 2))),
+                         "dual": float(theta * np.sqrt(np.sum((w - w_prev) ** 2)))})
+        w_hat = w + g * (w - w_prev)
+        b_hat = b + g * (b - b_prev)
+        w_prev, b_prev = w, b
+        alpha = alpha_next
+    return AdmmResult(w=w, b=b, v=v, gammas=np.array(gam), history=hist)
+
+
+# ---------------------------------------------------------------------------
+# Outer composition loop -- Sec. 2, Eq. (1) with N = 1
+# ---------------------------------------------------------------------------
+@dataclass
+class RegisterResult:
+    disp: np.ndarray
+    warped: np.ndarray
+    velocities: list
+
+
+def register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float,
+             order: int, outer: int, iters: int, data_term: int = 2,
+             init_disp: np.ndarray | None = None,
+             keep_velocities: bool = False) -> RegisterResult:
+    """The iterative scheme of Sec. 2: solve the model for a velocity with
+    the current warped source, compose it onto the deformation, warp the
+    original source again, repeat ``outer`` times.
+
+    Composition order (Sec. 2): phi_c = phi_{c-1} o (Id + v_c), so the
+    displacement becomes u_c(x) = v_c(x) + u_{c-1}(x + v_c(x))."""
+    fixed = np.asarray(fixed, dtype=np.float64)
+    moving = np.asarray(moving, dtype=np.float64)
+    u = np.zeros((3,) + fixed.shape) if init_disp is None else np.asarray(init_disp, np.float64).copy()
+    vels = []
+    for _ in range(outer):
+        _, J, r = warp_grad_residual(moving, fixed, u)
+        res = admm(J, r, lam, theta, order, iters, data_term=data_term)
+        vel = res.w
+        if keep_velocities:
+            vels.append(vel.copy())
+        u = compose(u, vel)
+    warped = trilinear_periodic(moving, u)
+    return RegisterResult(disp=u, warped=warped, velocities=vels)
+
+
+# ---------------------------------------------------------------------------
+# Jacobian-determinant check -- Sec. 4 (percentage of non-positive |J_phi|)
+# ---------------------------------------------------------------------------
+def jacobian_det(disp: np.ndarray) -> np.ndarray:
+    """det(I + D u) per voxel, D by periodic central differences."""
+    D = np.empty((3, 3) + disp.shape[1:])
+    for c in range(3):
+        for d in range(3):
+            D[c, d] = central_diff(disp[c], AXIS_OF_COMPONENT[d])
+    A = D + np.eye(3)[:, :, None, None, None]
+    return (A[0, 0] * (A[1, 1] * A[2, 2] - A[1, 2] * A[2, 1])
+            - A[0, 1] * (A[1, 0] * A[2, 2] - A[1, 2] * A[2, 0])
+            + A[0, 2] * (A[1, 0] * A[2, 1] - A[1, 1] * A[2, 0]))
+
+
+def jacobian_stats(disp: np.ndarray):
+    """(min det, max det, mean det, number of voxels with det <= 0)."""
+    d = jacobian_det(disp)
+    return float(d.min()), float(d.max()), float(d.mean()), int(np.count_nonzero(d <= 0))
+
+
+def ssd(a: np.ndarray, b: np.ndarray) -> float:
+    return float(np.sum((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))

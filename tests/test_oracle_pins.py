@@ -1,0 +1,443 @@
+"""Pins for the FP64 oracle: each test checks it against something the paper or
+the mathematics fixes, never against a re-typed copy of its own formula.
+
+Dense reference operators below are assembled from the stencils with explicit
+index loops (not the oracle's roll-based differences), on grids small enough
+for dense linear algebra.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle as O
+import synth
+
+
+# ---------------------------------------------------------------------------
+# dense reference operators (explicit index loops on tiny grids)
+# ---------------------------------------------------------------------------
+def _idx(x, y, z, d):
+    nx, ny, nz = d
+    return x + nx * (y + ny * z)
+
+
+def dense_neg_laplacian(d):
+    """The periodic 7-point -Delta with unit spacing as a V x V matrix."""
+    nx, ny, nz = d
+    V = nx * ny * nz
+    L = np.zeros((V, V))
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                i = _idx(x, y, z, d)
+                for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    L[i, i] += 1.0
+                    L[i, _idx((x + dx) % nx, (y + dy) % ny, (z + dz) % nz, d)] -= 1.0
+    return L
+
+
+def dense_central_diff(d, axis_xyz):
+    nx, ny, nz = d
+    V = nx * ny * nz
+    D = np.zeros((V, V))
+    step = [(1, 0, 0), (0, 1, 0), (0, 0, 1)][axis_xyz]
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                i = _idx(x, y, z, d)
+                jp = _idx((x + step[0]) % nx, (y + step[1]) % ny, (z + step[2]) % nz, d)
+                jm = _idx((x - step[0]) % nx, (y - step[1]) % ny, (z - step[2]) % nz, d)
+                D[i, jp] += 0.5
+                D[i, jm] -= 0.5
+    return D
+
+
+def flat(f):
+    """(nz, ny, nx) -> x-fastest vector, matching _idx."""
+    return f.reshape(-1)
+
+
+def model_minimiser(J, r, lam, order):
+    """Brute-force minimiser of Eq. (2) with s = 2 for the regulariser
+    <v, (-Delta_h)^n v>: solve (blockdiag(J J^T) + lam I_3 (x) L^n) v = -J r."""
+    d = (J.shape[3], J.shape[2], J.shape[1])
+    V = J[0].size
+    Ln = np.linalg.matrix_power(dense_neg_laplacian(d), order)
+    Jf = J.reshape(3, V)
+    A = np.zeros((3 * V, 3 * V))
+    for c in range(3):
+        for e in range(3):
+            A[c * V + np.arange(V), e * V + np.arange(V)] += Jf[c] * Jf[e]
+        A[c * V:(c + 1) * V, c * V:(c + 1) * V] += lam * Ln
+    rhs = -(Jf * r.reshape(V)).reshape(-1)
+    return np.linalg.solve(A, rhs).reshape(J.shape)
+
+
+# ---------------------------------------------------------------------------
+# P1  Nesterov scalars (Sec. 3, Eq. (5))
+# ---------------------------------------------------------------------------
+def test_p1_nesterov_scalars():
+    a = O.nesterov_alphas(40)
+    g = O.nesterov_gammas(40)
+    assert a[0] == 1.0
+    # alpha^1 is the golden ratio; gamma_0 = 0 exactly (no momentum at k = 0, 1)
+    assert a[1] == pytest.approx((1 + math.sqrt(5)) / 2, abs=1e-15)
+    assert g[0] == 0.0
+    # every alpha^{k+1} is the positive root of t^2 - t - (alpha^k)^2 = 0
+    for k in range(40):
+        t = a[k + 1]
+        assert t * t - t == pytest.approx(a[k] ** 2, rel=1e-14)
+        assert t > 0
+    # growth bounds of the accelerated sequence: (k+2)/2 <= alpha^k <= k+1
+    for k in range(1, 41):
+        assert (k + 2) / 2.0 <= a[k] <= k + 1
+    # gamma_1 from the closed form of alpha^1, alpha^2
+    phi = (1 + math.sqrt(5)) / 2
+    assert g[1] == pytest.approx((phi - 1) / ((1 + math.sqrt(1 + 4 * phi * phi)) / 2), rel=1e-15)
+    assert np.all(np.diff(g) > 0) and g[-1] < 1.0
+
+
+# ---------------------------------------------------------------------------
+# P2  Laplacian symbol (Sec. 3, text after Eq. (6))
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [(4, 4, 4), (5, 5, 5), (6, 4, 3)])
+def test_p2_symbol_is_dense_laplacian_spectrum(d):
+    L = dense_neg_laplacian(d)
+    sym = O.laplacian_symbol(d, half=False)
+    # sorted spectrum equals the symbol over the full DFT grid
+    ev = np.linalg.eigvalsh(L)
+    assert np.allclose(np.sort(ev), np.sort(sym.ravel()), atol=1e-12)
+    # every plane wave is an eigenvector with the symbol as eigenvalue
+    nx, ny, nz = d
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for (p, q, r) in [(1, 0, 0), (0, 1, 2), (2, 3, 1), (nx - 1, ny - 1, nz - 1)]:
+        e = np.exp(2j * np.pi * (p * xx / nx + q * yy / ny + r * zz / nz))
+        Le = L @ flat(e)
+        assert np.allclose(Le, sym[r, q, p] * flat(e), atol=1e-12)
+    assert sym[0, 0, 0] == 0.0 and np.all(sym >= 0)
+
+
+# ---------------------------------------------------------------------------
+# P3  Sherman-Morrison v-step (Eq. (6), s = 2)
+# ---------------------------------------------------------------------------
+def test_p3_sherman_morrison_matches_dense_3x3():
+    rng = np.random.default_rng(3)
+    d = (5, 4, 3)
+    J = rng.standard_normal((3, 3, 4, 5))
+    a = rng.standard_normal((3, 3, 4, 5))
+    r = rng.standard_normal((3, 4, 5))
+    theta = 0.37
+    v = O.v_step_l2(a, J, r, theta)
+    for z in range(3):
+        for y in range(4):
+            for x in range(5):
+                j = J[:, z, y, x]
+                M = np.outer(j, j) + theta * np.eye(3)
+                ref = np.linalg.solve(M, theta * a[:, z, y, x] - j * r[z, y, x])
+                assert np.allclose(v[:, z, y, x], ref, rtol=1e-13, atol=1e-14)
+    # v minimises the data subproblem: gradient vanishes
+    rho = np.sum(J * v, axis=0) + r
+    grad = J * rho[None] + theta * (v - a)
+    assert np.abs(grad).max() < 1e-12
+
+
+def test_p3b_l1_vstep_minimises_subproblem():
+    """s = 1: v minimises |<J,v> + r| + theta/2 |v - a|^2 per voxel (checked
+    by a 1-D search along J, the only direction the data term sees)."""
+    rng = np.random.default_rng(4)
+    J = rng.standard_normal((3, 2, 2, 2))
+    a = rng.standard_normal((3, 2, 2, 2))
+    r = rng.standard_normal((2, 2, 2))
+    theta = 0.5
+    v = O.v_step_l1(a, J, r, theta, eps=0.0)
+    for idx in np.ndindex(2, 2, 2):
+        j, aa, rr, vv = J[(slice(None),) + idx], a[(slice(None),) + idx], r[idx], v[(slice(None),) + idx]
+        f = lambda u: abs(j @ u + rr) + theta / 2 * np.sum((u - aa) ** 2)
+        ts = np.linspace(-5, 5, 200001)
+        best = min(f(aa + t * j) for t in ts[::50])
+        assert f(vv) <= best + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# P4  Fourier w-step (Eq. (6) bottom, read with theta in the numerator)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d,order", [((4, 4, 4), 1), ((4, 4, 4), 2), ((6, 4, 3), 3), ((5, 3, 4), 2)])
+def test_p4_fourier_solve_equals_dense_solve(d, order):
+    rng = np.random.default_rng(11)
+    lam, theta = 0.7, 0.2
+    nx, ny, nz = d
+    s = rng.standard_normal((3, nz, ny, nx))
+    w = O.fourier_solve(s, O.w_step_multiplier(d, lam, theta, order))
+    A = lam * np.linalg.matrix_power(dense_neg_laplacian(d), order) + theta * np.eye(nx * ny * nz)
+    for c in range(3):
+        ref = np.linalg.solve(A, theta * flat(s[c]))
+        assert np.allclose(flat(w[c]), ref, rtol=1e-12, atol=1e-13)
+
+
+def test_p4_plane_wave_dc_and_self_adjoint():
+    d = (8, 6, 4)
+    nx, ny, nz = d
+    lam, theta, order = 0.3, 0.1, 2
+    m = O.w_step_multiplier(d, lam, theta, order)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    p, q, r = 3, 2, 1
+    wave = np.cos(2 * np.pi * (p * xx / nx + q * yy / ny + r * zz / nz))
+    k = (2 * (3 - np.cos(2 * np.pi * p / nx) - np.cos(2 * np.pi * q / ny) - np.cos(2 * np.pi * r / nz))) ** order
+    out = O.fourier_solve(np.stack([wave] * 3), m)
+    assert np.allclose(out[0], theta / (theta + lam * k) * wave, atol=1e-14)
+    const = np.full((3, nz, ny, nx), 2.5)
+    assert np.allclose(O.fourier_solve(const, m), const, atol=1e-14)
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal((2, 3, nz, ny, nx))
+    assert np.sum(O.fourier_solve(x, m) * y) == pytest.approx(np.sum(x * O.fourier_solve(y, m)), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P5  whole ADMM against the brute-force minimiser of the model (4^3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("order,lam", [(1, 0.1), (2, 0.01), (2, 0.5), (3, 0.1)])
+def test_p5_admm_converges_to_dense_minimiser(order, lam):
+    rng = np.random.default_rng(100 + order)
+    J = rng.uniform(-0.3, 0.3, size=(3, 4, 4, 4))
+    r = rng.uniform(-0.5, 0.5, size=(4, 4, 4))
+    vstar = model_minimiser(J, r, lam, order)
+    res = O.admm(J, r, lam, 0.1, order, 1000)
+    scale = np.abs(vstar).max()
+    assert np.abs(res.w - vstar).max() / scale < 1e-10
+    assert np.abs(res.v - vstar).max() / scale < 1e-10
+
+
+def test_p5_planted_literal_wstep_fails():
+    """The w-step as printed (no theta in the numerator) does not reach the
+    model's minimiser: the pins above reject that reading."""
+    rng = np.random.default_rng(102)
+    d = (4, 4, 4)
+    J = rng.uniform(-0.3, 0.3, size=(3, 4, 4, 4))
+    r = rng.uniform(-0.5, 0.5, size=(4, 4, 4))
+    lam, theta, order = 0.01, 0.1, 2
+    vstar = model_minimiser(J, r, lam, order)
+    literal = 1.0 / (lam * O.laplacian_symbol(d) ** order + theta)
+    with np.errstate(all="ignore"):
+        res = O.admm(J, r, lam, theta, order, 300, mult=literal)
+        err = np.abs(res.w - vstar).max() / np.abs(vstar).max()
+    assert not (err < 1e-3)
+
+
+# ---------------------------------------------------------------------------
+# P6  special cases
+# ---------------------------------------------------------------------------
+def test_p6_lambda_zero_gives_normal_flow():
+    rng = np.random.default_rng(6)
+    J = rng.uniform(0.2, 0.6, size=(3, 4, 4, 4)) * rng.choice([-1, 1], size=(3, 4, 4, 4))
+    r = rng.uniform(-0.5, 0.5, size=(4, 4, 4))
+    res = O.admm(J, r, 0.0, 0.1, 2, 400)
+    normal = -J * (r / np.sum(J * J, axis=0))[None]
+    assert np.abs(res.w - normal).max() < 1e-10
+
+
+def test_p6_first_iteration_from_zero():
+    rng = np.random.default_rng(7)
+    d = (6, 4, 4)
+    J = rng.standard_normal((3, 4, 4, 6))
+    r = rng.standard_normal((4, 4, 6))
+    lam, theta, order = 0.2, 0.3, 1
+    res = O.admm(J, r, lam, theta, order, 1)
+    v0 = -J * (r / (theta + np.sum(J * J, axis=0)))[None]
+    A = lam * dense_neg_laplacian(d) + theta * np.eye(96)
+    w0 = np.stack([np.linalg.solve(A, theta * flat(v0[c])).reshape(4, 4, 6) for c in range(3)])
+    assert np.allclose(res.v, v0, atol=1e-14)
+    assert np.allclose(res.w, w0, atol=1e-13)
+    assert np.allclose(res.b, v0 - w0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# P7  identity: fixed == moving gives exactly zero
+# ---------------------------------------------------------------------------
+def test_p7_identity_is_exact_zero():
+    img = synth.random_volume((12, 10, 8), seed=3, smooth_kmax=3).astype(np.float64)
+    res = O.register(img, img, 0.01, 0.1, 2, 3, 5)
+    assert np.count_nonzero(res.disp) == 0
+    assert np.array_equal(res.warped, img)
+
+
+# ---------------------------------------------------------------------------
+# P8  recovery of a known integer translation
+# ---------------------------------------------------------------------------
+def test_p8_known_translation():
+    pair = synth.make_pair("blobs32")
+    moving = pair.moving.astype(np.float64)
+    fixed = np.roll(moving, -1, axis=2)  # fixed(x) = moving(x + e_x): true u = (1, 0, 0)
+    res = O.register(fixed, moving, 0.01, 0.01, 2, 10, 100)
+    assert abs(res.disp[0].mean() - 1.0) < 0.05
+    gmag = np.sqrt(np.sum(O.gradient(moving) ** 2, axis=0))
+    mask = gmag > 0.02
+    err = np.sqrt((res.disp[0] - 1.0) ** 2 + res.disp[1] ** 2 + res.disp[2] ** 2)
+    assert err[mask].mean() < 0.05
+
+
+# ---------------------------------------------------------------------------
+# P9  adjoints and the sign/scale of the central difference
+# ---------------------------------------------------------------------------
+def test_p9_gradient_matches_dense_stencil_and_adjoint():
+    d = (5, 4, 3)
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((3, 4, 5))
+    g = O.gradient(f)
+    for ax in range(3):
+        assert np.allclose(flat(g[ax]), dense_central_diff(d, ax) @ flat(f), atol=1e-14)
+    gv = rng.standard_normal((3, 3, 4, 5))
+    div = sum(dense_central_diff(d, ax) @ flat(gv[ax]) for ax in range(3))
+    assert np.sum(g * gv) == pytest.approx(-np.dot(flat(f), div), rel=1e-12)
+
+
+def test_p9_gradient_of_plane_wave():
+    n = 16
+    zz, yy, xx = np.meshgrid(np.arange(8), np.arange(12), np.arange(n), indexing="ij")
+    f = np.sin(2 * np.pi * xx / n)
+    g = O.gradient(f)
+    assert np.allclose(g[0], np.sin(2 * np.pi / n) * np.cos(2 * np.pi * xx / n), atol=1e-14)
+    assert np.abs(g[1]).max() == 0 and np.abs(g[2]).max() == 0
+
+
+def test_p9_rfft_roundtrip_identity():
+    rng = np.random.default_rng(2)
+    s = rng.standard_normal((3, 6, 4, 8))
+    ones = np.ones((6, 4, 5))
+    assert np.allclose(O.fourier_solve(s, ones), s, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# P10 Jacobian determinant closed forms
+# ---------------------------------------------------------------------------
+def test_p10_jacobian_closed_form():
+    nx, ny, nz = 16, 8, 6
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    A = 0.8
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = A * np.sin(2 * np.pi * xx / nx)
+    det = O.jacobian_det(u)
+    assert np.allclose(det, 1 + A * np.sin(2 * np.pi / nx) * np.cos(2 * np.pi * xx / nx), atol=1e-14)
+    u[:] = np.array([0.3, -1.7, 2.2])[:, None, None, None]
+    assert np.allclose(O.jacobian_det(u), 1.0, atol=0)
+    # a linear map x -> M x (periodic-compatible only through the stencil on
+    # interior voxels): det(I + D u) = det(M) away from the wrap-around
+    rng = np.random.default_rng(10)
+    Mx = rng.uniform(-0.2, 0.2, size=(3, 3))
+    coords = np.stack([xx, yy, zz]).astype(np.float64)
+    u = np.einsum("cd,d...->c...", Mx, coords)
+    det = O.jacobian_det(u)
+    assert det[2, 3, 5] == pytest.approx(np.linalg.det(np.eye(3) + Mx), rel=1e-12)
+    mn, mx, mean, nneg = O.jacobian_stats(np.zeros((3, 4, 4, 4)))
+    assert (mn, mx, mean, nneg) == (1.0, 1.0, 1.0, 0)
+
+
+# ---------------------------------------------------------------------------
+# P11 compose and scaling-and-squaring
+# ---------------------------------------------------------------------------
+def test_p11_compose_identities():
+    d = (10, 8, 6)
+    u = synth.random_vector_field(d, seed=4, amp=2.0, smooth_kmax=2).astype(np.float64)
+    z = np.zeros_like(u)
+    assert np.allclose(O.compose(u, z), u, atol=0)
+    assert np.allclose(O.compose(z, u), u, atol=0)
+    # integer translations add exactly
+    t1 = np.broadcast_to(np.array([2.0, -3.0, 1.0])[:, None, None, None], u.shape).copy()
+    t2 = np.broadcast_to(np.array([-5.0, 1.0, 4.0])[:, None, None, None], u.shape).copy()
+    assert np.array_equal(O.compose(t1, t2), t1 + t2)
+    # composing with an integer shift samples u at the shifted voxel
+    c = O.compose(u, t1)
+    assert np.allclose(c, t1 + np.roll(u, shift=(-1, 3, -2), axis=(1, 2, 3)), atol=1e-14)
+    assert np.allclose(O.expmap(t1 * 0.37, 6), t1 * 0.37, atol=1e-14)
+
+
+def test_p11_expmap_converges_to_flow():
+    """Scaling and squaring approaches the time-1 flow of the stationary field
+    (computed independently by RK4 on a cubic-spline field) as K grows."""
+    d = (32, 32, 32)
+    rng = np.random.default_rng(12)
+    vel = 1.5 * synth.band_limited_field(d, rng, kmax=1)
+    coeffs = synth.generators._spline_coeffs(vel)
+    xx, yy, zz = synth.grid(d)
+    ref = synth.flow(coeffs, 1.0, xx, yy, zz, steps=16)
+    errs = [np.abs(O.expmap(vel, K) - ref).max() for K in (0, 2, 4, 6)]
+    # the error falls with K down to the trilinear interpolation floor
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < 0.15 * errs[0] and errs[3] < 0.015 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# P12 trilinear resampling equals SciPy's periodic linear interpolation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("amp", [0.7, 9.3])
+def test_p12_trilinear_matches_scipy(amp):
+    d = (9, 7, 5)
+    rng = np.random.default_rng(13)
+    f = rng.standard_normal((5, 7, 9))
+    u = amp * rng.standard_normal((3, 5, 7, 9))
+    xx, yy, zz = synth.grid(d)
+    ref = ndimage.map_coordinates(f, np.stack([(zz + u[2]).ravel(), (yy + u[1]).ravel(), (xx + u[0]).ravel()]),
+                                  order=1, mode="grid-wrap").reshape(f.shape)
+    assert np.allclose(O.trilinear_periodic(f, u), ref, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P13 invariants of the iteration and of the whole registration
+# ---------------------------------------------------------------------------
+def test_p13_iteration_invariants():
+    rng = np.random.default_rng(14)
+    J = 0.3 * rng.standard_normal((3, 6, 8, 10))
+    r = 0.3 * rng.standard_normal((6, 8, 10))
+    res = O.admm(J, r, 0.05, 0.1, 2, 12, history=True)
+    m = O.w_step_multiplier((10, 8, 6), 0.05, 0.1, 2)
+    for h in res.history:
+        assert np.abs(h["b"].mean(axis=(1, 2, 3))).max() < 1e-14
+    # the w-step never increases the l2 norm (0 < multiplier <= 1)
+    s = rng.standard_normal((3, 6, 8, 10))
+    assert np.linalg.norm(O.fourier_solve(s, m)) <= np.linalg.norm(s)
+
+
+def test_p13_registration_equivariance():
+    pair = synth.make_pair("blobs32")
+    f, mv = pair.fixed.astype(np.float64), pair.moving.astype(np.float64)
+    base = O.register(f, mv, 0.01, 0.1, 2, 2, 4)
+    # integer periodic roll
+    sh = (3, -5, 7)
+    rolled = O.register(np.roll(f, sh, axis=(0, 1, 2)), np.roll(mv, sh, axis=(0, 1, 2)), 0.01, 0.1, 2, 2, 4)
+    assert np.allclose(rolled.disp, np.roll(base.disp, sh, axis=(1, 2, 3)), atol=1e-12)
+    # swapping the x and y axes swaps the x and y displacement components
+    ft, mt = np.swapaxes(f, 1, 2), np.swapaxes(mv, 1, 2)
+    sw = O.register(ft, mt, 0.01, 0.1, 2, 2, 4)
+    expect = np.stack([np.swapaxes(base.disp[1], 1, 2), np.swapaxes(base.disp[0], 1, 2),
+                       np.swapaxes(base.disp[2], 1, 2)])
+    assert np.allclose(sw.disp, expect, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P14 positivity of the Jacobian on the 32^3 blob workload
+# ---------------------------------------------------------------------------
+def test_p14_blob_workload_is_diffeomorphic_and_improves():
+    pair = synth.make_pair("blobs32")
+    w = synth.WORKLOADS["blobs32"]
+    res = O.register(pair.fixed, pair.moving, w["lam"], w["theta"], w["order"], w["outer"], w["iters"])
+    mn, mx, mean, nneg = O.jacobian_stats(res.disp)
+    assert nneg == 0 and mn > 0
+    assert O.ssd(pair.fixed, res.warped) < 0.1 * O.ssd(pair.fixed, pair.moving)
+
+
+# ---------------------------------------------------------------------------
+# P15 the un-restarted accelerated iteration can diverge (documented)
+# ---------------------------------------------------------------------------
+def test_p15_divergence_is_visible_in_residuals():
+    rng = np.random.default_rng(15)
+    J = rng.choice([-1.0, 1.0], size=(3, 4, 4, 4)) / math.sqrt(3)  # |J| = 1
+    r = rng.uniform(-0.5, 0.5, size=(4, 4, 4))
+    with np.errstate(all="ignore"):
+        res = O.admm(J, r, 10.0, 0.1, 1, 200, history=True)
+    p = np.array([h["primal"] for h in res.history])
+    assert not np.isfinite(p[-1]) or p[-1] > 10 * p[:50].min()
+    # the safe regime (small |J| and lambda) converges
+    res2 = O.admm(0.3 * J, r, 0.5, 0.1, 1, 200, history=True)
+    p2 = np.array([h["primal"] for h in res2.history])
+    assert p2[-1] < 1e-8 * p2[0]
