@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark: registrations/s and ms per ADMM iteration of the HIP path.
+
+One step = one full registration (every stage of the path) of the 128x128x96
+nested-ellipsoid heart phantom pair, 10 warpings x 20 Nesterov-ADMM
+iterations, n = 2, lambda = 0.01, theta = 0.1, with inputs already resident
+in GPU memory.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+# Algorithmic bytes per voxel of each kernel kind (inputs read once, outputs
+# written once; float32 fields, packed half spectrum = 4 B per component).
+BYTES_PER_VOXEL = {
+    "pass_a_fwd_x": None,        # 36 with extrapolation (reads s^k, s^{k-1}), 24 without
+    "pass_b_yz_solve": 24.0,     # read + write the 3-component half spectrum
+    "pass_c_iter": 64.0,         # spectrum 12 + s^k, s^{k-1} 24 + J 12 + r 4, write s 12
+    "pass_c_compose": 44.0,      # spectrum 12 + u gather 12 + image gather 4, write u 12 + I^w 4
+    "grad_resid": 36.0,          # I^w 4 + I0 4, write J 12 + r 4 + s^0 12
+    "warp": 20.0,                # u 12 + image 4, write 4
+    "fill": 12.0,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="phantom128x128x96")
+    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pair, w):
+    """The FP64 oracle on a bounded sample: one warping (warp, gradient,
+    `iters` ADMM iterations, composition) of the same workload, scaled to
+    registrations/s (a registration is `outer` such warpings)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+
+    fixed = pair.fixed.astype(np.float64)
+    moving = pair.moving.astype(np.float64)
+    u = np.zeros((3,) + fixed.shape)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, J, r = O.warp_grad_residual(moving, fixed, u)
+        res = O.admm(J, r, w["lam"], w["theta"], w["order"], w["iters"])
+        O.compose(u, res.w)
+        dt = time.perf_counter() - t0
+    return {"value": 1.0 / (w["outer"] * dt), "unit": "registrations/s", "cores": 1, "kind": "oracle",
+            "sample": f"one warping ({w['iters']} ADMM iterations + warp + compose) of {w['outer']}, "
+                      f"numpy float64 single thread, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
+              "part of this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2109_12688_amd import _lib, api
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    log(f"generating {args.workload}")
+    pair = synth.make_pair(args.workload)
+    fixed = torch.from_numpy(pair.fixed).cuda()
+    moving = torch.from_numpy(pair.moving).cuda()
+    shp = tuple(fixed.shape)
+    V = int(np.prod(shp))
+    ws = api.workspace(shp)
+    out = {"disp": torch.empty((3,) + shp, device="cuda"), "warped": torch.empty(shp, device="cuda")}
+
+    def step():
+        return api.register(fixed, moving, w["lam"], w["theta"], w["order"], w["outer"], w["iters"],
+                            ws=ws, out=out)
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"timing {args.steps} registrations")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    log(f"{ms_per_step:.3f} ms/registration (wall {1e3 * wall / args.steps:.3f})")
+
+    # per-kernel durations from HIP events bracketing each library launch
+    _lib.profile_enable(True)
+    for _ in range(args.profile_steps):
+        step()
+    torch.cuda.synchronize()
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    kernels = {}
+    for k, (n, ms) in prof.items():
+        kernels[k] = {"launches_per_step": n / args.profile_steps, "avg_us": 1e3 * ms / n}
+    n_iter = w["outer"] * (w["iters"] - 1)
+    per_iter_us = sum(1e3 * prof[k][1] for k in ("pass_a_fwd_x", "pass_b_yz_solve", "pass_c_iter")
+                      if k in prof) / max(1, args.profile_steps * n_iter)
+    # pass A runs with extrapolation (iters-1 per warping) and without (1 per warping)
+    na = w["iters"] - 1
+    BYTES_PER_VOXEL["pass_a_fwd_x"] = (36.0 * na + 24.0) / (na + 1)
+    dom = max((k for k in prof if k in BYTES_PER_VOXEL), key=lambda k: prof[k][1])
+    avg_s = prof[dom][1] / prof[dom][0] / 1e3
+    achieved = BYTES_PER_VOXEL[dom] * V / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "bytes_per_launch": BYTES_PER_VOXEL[dom] * V, "avg_us": round(avg_s * 1e6, 3),
+                "traffic": None}
+
+    stats, nneg, _ = api.jacobian(out["disp"], ws=ws)
+    torch.cuda.synchronize()
+    res = {
+        "metric": "registrations/sec + ms per ADMM iter at 128x128x96; batched/BF16 vs plain",
+        "value": round(1000.0 / ms_per_step, 3),
+        "unit": "registrations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_admm_iter": round(per_iter_us / 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims_xyz": list(w["dims"]), "outer": w["outer"],
+                   "iters": w["iters"], "order": w["order"], "lambda": w["lam"], "theta": w["theta"],
+                   "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "min_det_J": float(stats[0].item()),
+        "n_det_nonpos": int(nneg.item()),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle sample on the CPU")
+        res["cpu_baseline"] = cpu_baseline(pair, w)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

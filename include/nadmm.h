@@ -1,0 +1,173 @@
+/*
+ * nadmm.h -- C ABI of the MI355X (gfx950) library for Nesterov-accelerated
+ * ADMM diffeomorphic registration (Thorley et al., "Nesterov Accelerated ADMM
+ * for Fast Diffeomorphic Image Registration").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Every array argument is a DEVICE pointer (hipMalloc'd or a torch
+ *           CUDA/ROCm tensor's data pointer) unless its comment says "host".
+ *           The caller owns every buffer; the library never allocates device
+ *           memory.  Buffers must stay alive until the enqueued work has run.
+ * Layout.   A scalar volume holds nx*ny*nz float32 values, voxel (x, y, z) at
+ *           index x + nx*(y + ny*z) (x fastest; a torch tensor of shape
+ *           (nz, ny, nx)).  A vector field holds three such volumes back to
+ *           back: component 0 is the x displacement, 1 the y, 2 the z
+ *           (torch shape (3, nz, ny, nx)).  Displacements and velocities are in
+ *           voxel units.  Deformations are backward (pull): the image warped
+ *           by displacement u is I(x + u(x)).  Boundaries are periodic
+ *           everywhere (resampling, finite differences and the Fourier solve).
+ * Alignment. Every array pointer must be 16-byte aligned.
+ * Streams.   `stream` is a hipStream_t passed as void* (NULL = the null
+ *           stream).  Every call only enqueues work on that stream and
+ *           returns; results are valid after the caller synchronises it.
+ * Errors.   Every entry point validates all arguments before it enqueues
+ *           anything, so a call that returns an error has enqueued nothing.
+ *           HIP runtime failures return NADMM_ERR_HIP.  nadmm_last_error()
+ *           gives a per-thread message for the last non-OK status.
+ * Sizes.    nx and ny must be even; every dimension must be 2^a * 3^b with
+ *           4 <= n <= 256, and ny*nz <= 16384 (the y-z spectral plane must
+ *           fit one compute unit's local memory).  Other sizes return
+ *           NADMM_ERR_UNSUPPORTED_SIZE.
+ */
+#ifndef NADMM_H
+#define NADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NADMM_ABI_VERSION 1
+
+typedef enum {
+  NADMM_OK = 0,
+  NADMM_ERR_INVALID_ARG = 1,      /* null/misaligned pointer, bad parameter value   */
+  NADMM_ERR_UNSUPPORTED_SIZE = 2, /* dimensions outside the supported set above      */
+  NADMM_ERR_WORKSPACE = 3,        /* workspace missing or smaller than required      */
+  NADMM_ERR_HIP = 4               /* a HIP runtime call failed (message in last_error) */
+} nadmm_status;
+
+typedef struct {
+  int32_t nx, ny, nz;
+} nadmm_dims;
+
+/* Model and loop parameters.
+ *   lambda     regularisation weight lambda >= 0 of Eq. (2).
+ *   theta      ADMM penalty theta > 0 of Eq. (4).
+ *   order      regulariser order n, 1 <= n <= 4 (Eq. (2); the w-step divides
+ *              by theta + lambda * (2(3 - cos - cos - cos))^n, Sec. 3).
+ *   data_term  s of Eq. (2): 2 = squared L2 (Sherman-Morrison v-step),
+ *              1 = L1 (clipped v-step, Eq. (6) top).
+ *   eps        L1 only: the positive constant in the denominator of z_hat
+ *              (Sec. 3, text after Eq. (6)); ignored for data_term = 2.
+ *   outer      number of warpings (velocity fields composed, Eq. (1), N = 1).
+ *   iters      ADMM iterations per warping (Eq. (5)), >= 1.
+ */
+typedef struct {
+  double lambda;
+  double theta;
+  int32_t order;
+  int32_t data_term;
+  double eps;
+  int32_t outer;
+  int32_t iters;
+} nadmm_params;
+
+/* NADMM_ABI_VERSION of the loaded library. */
+int nadmm_abi_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* nadmm_status_string(nadmm_status s);
+
+/* Message describing the last non-OK status returned on the calling thread
+ * (static per-thread buffer, overwritten by the next failing call). */
+const char* nadmm_last_error(void);
+
+/* Size in bytes (written to host *bytes) of the workspace that every entry
+ * point below accepts for these dimensions.  `p` may be NULL (the size does
+ * not depend on the parameters).  About 17 float32 values per voxel. */
+nadmm_status nadmm_workspace_size(nadmm_dims d, const nadmm_params* p, size_t* bytes);
+
+/* Full registration: the iterative scheme of Sec. 2 with the
+ * Nesterov-accelerated ADMM of Sec. 3 (Eq. (5), (6)).
+ * For c = 1..outer: warp the ORIGINAL moving image by the current
+ * displacement, form the linearised data term (periodic central-difference
+ * gradient of the warped image and the residual warped - fixed), run `iters`
+ * ADMM iterations from zero (alpha^0 = 1), take the final w iterate as the
+ * warping's velocity v_c and compose: u <- v_c + u(x + v_c(x)).
+ *   fixed, moving  in, scalar volumes (I0 target, I1 source).
+ *   init_disp      in, vector field or NULL (NULL = start from u = 0).
+ *   disp           out, vector field: the final displacement u (phi = Id + u).
+ *   warped         out, scalar volume or NULL: moving(x + u(x)).
+ *   velocities     out, `outer` vector fields back to back, or NULL.
+ *   workspace      device scratch of at least nadmm_workspace_size bytes.
+ * Outputs must not overlap inputs or each other. */
+nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p,
+                            const float* fixed, const float* moving,
+                            const float* init_disp, float* disp, float* warped,
+                            float* velocities, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/* One ADMM solve (Eq. (5), (6)) for a given linearised data term:
+ * `p->iters` iterations from zero with J = grad I1^w (vector field) and
+ * r = I1^w - I0 (scalar volume).  Writes the final iterates w (vector
+ * field), b (vector field, may be NULL) and v (vector field, may be NULL).
+ * p->outer is ignored. */
+nadmm_status nadmm_admm(nadmm_dims d, const nadmm_params* p, const float* J,
+                        const float* r, float* w_out, float* b_out, float* v_out,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* The Fourier-diagonalised w-step alone (Eq. (6) bottom, read with theta in
+ * the numerator): w = F^-1[ theta F(s) / (theta + lambda (2(3 - cos(2 pi p/nx)
+ * - cos(2 pi q/ny) - cos(2 pi r/nz)))^n) ] per component.  Uses lambda,
+ * theta and order of `p`.  s and w are vector fields (may be the same
+ * pointer). */
+nadmm_status nadmm_fourier_solve(nadmm_dims d, const nadmm_params* p, const float* s,
+                                 float* w, void* workspace, size_t workspace_bytes,
+                                 void* stream);
+
+/* Periodic trilinear warp (Sec. 2): out(x) = img(x + disp(x)).  If `grad` is
+ * not NULL also writes the periodic central-difference gradient of `out`
+ * (vector field); if `resid` is not NULL (requires `ref`) writes
+ * out - ref.  `out` must not alias img or disp. */
+nadmm_status nadmm_warp(nadmm_dims d, const float* img, const float* disp, const float* ref,
+                        float* out, float* grad, float* resid, void* stream);
+
+/* Composition of displacements (Eq. (1)): out(x) = v(x) + u(x + v(x)), the
+ * displacement of (Id + u) o (Id + v).  out must not alias u or v. */
+nadmm_status nadmm_compose(nadmm_dims d, const float* u, const float* v, float* out,
+                           void* stream);
+
+/* Scaling and squaring of a stationary velocity field: u = vel / 2^steps,
+ * then `steps` self-compositions u <- u + u(x + u(x)).  0 <= steps <= 30.
+ * out must not alias vel. */
+nadmm_status nadmm_expmap(nadmm_dims d, const float* vel, int32_t steps, float* out,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Jacobian-determinant check (Sec. 4): det(I + D disp) per voxel with periodic
+ * central differences, evaluated and reduced in float64.
+ *   det        out, scalar volume or NULL.
+ *   stats      out, device double[3]: min, max and mean of the determinant.
+ *   n_nonpos   out, device int64[1]: number of voxels with det <= 0.
+ * The reduction order is fixed, so results are bitwise reproducible. */
+nadmm_status nadmm_jacobian(nadmm_dims d, const float* disp, float* det, double* stats,
+                            int64_t* n_nonpos, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/* Kernel timing instrumentation, for benchmarks.  While enabled (enable != 0),
+ * every kernel the library launches is bracketed by two HIP events recorded
+ * on its stream.  Host-side bookkeeping only; no device memory is used.
+ * nadmm_profile_read() waits for the recorded events, writes for up to `max`
+ * kernel kinds their static name, launch count and summed event-to-event
+ * milliseconds since the previous read (host arrays, any may be NULL), clears
+ * the records and returns the number of kinds (or -1 on a HIP failure). */
+nadmm_status nadmm_profile_enable(int enable);
+int nadmm_profile_read(int max, const char** names, int64_t* counts, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NADMM_H */

@@ -1,0 +1,178 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only).
+
+Volumes are float32 tensors of shape (nz, ny, nx) and vector fields of shape
+(3, nz, ny, nx) (component 0 = x), contiguous, on the ROCm device.  Every
+function enqueues its work on torch's current stream and returns tensors
+whose values are valid in stream order (as with any torch op).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import Dims, Params
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(t, name, shape=None, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+
+
+def dims_of(vol_shape) -> Dims:
+    nz, ny, nx = vol_shape[-3:]
+    return Dims(nx, ny, nz)
+
+
+def params(lam: float, theta: float, order: int, outer: int = 1, iters: int = 1,
+           data_term: int = 2, eps: float = 1e-8) -> Params:
+    return Params(float(lam), float(theta), int(order), int(data_term), float(eps), int(outer),
+                  int(iters))
+
+
+def workspace_size(vol_shape) -> int:
+    n = ctypes.c_size_t(0)
+    _lib.call("nadmm_workspace_size", dims_of(vol_shape), None, ctypes.byref(n))
+    return int(n.value)
+
+
+def workspace(vol_shape, device="cuda") -> torch.Tensor:
+    """A workspace tensor usable by every entry point for these dimensions."""
+    return torch.empty(workspace_size(vol_shape), dtype=torch.uint8, device=device)
+
+
+def _ws(vol_shape, ws, device):
+    if ws is None:
+        ws = workspace(vol_shape, device)
+    _check(ws, "workspace", dtype=torch.uint8)
+    return ws
+
+
+def register(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
+             outer: int, iters: int, data_term: int = 2, eps: float = 1e-8,
+             init_disp: torch.Tensor | None = None, return_velocities: bool = False,
+             ws: torch.Tensor | None = None, out: dict | None = None) -> dict:
+    """Full registration (Sec. 2 scheme with Sec. 3 ADMM).  Returns a dict with
+    'disp' (3, nz, ny, nx), 'warped' (nz, ny, nx) and optionally 'velocities'
+    (outer, 3, nz, ny, nx).  ``out`` may supply preallocated output tensors."""
+    _check(fixed, "fixed")
+    shp = tuple(fixed.shape)
+    _check(moving, "moving", shp)
+    vshp = (3,) + shp
+    if init_disp is not None:
+        _check(init_disp, "init_disp", vshp)
+    out = dict(out or {})
+    dev = fixed.device
+    disp = out.get("disp")
+    if disp is None:
+        disp = torch.empty(vshp, dtype=torch.float32, device=dev)
+    warped = out.get("warped")
+    if warped is None:
+        warped = torch.empty(shp, dtype=torch.float32, device=dev)
+    vels = out.get("velocities")
+    if return_velocities and vels is None:
+        vels = torch.empty((outer,) + vshp, dtype=torch.float32, device=dev)
+    ws = _ws(shp, ws, dev)
+    p = params(lam, theta, order, outer, iters, data_term, eps)
+    _lib.call("nadmm_register", dims_of(shp), ctypes.byref(p), _ptr(fixed), _ptr(moving),
+              _ptr(init_disp), _ptr(disp), _ptr(warped), _ptr(vels) if return_velocities else None,
+              _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    res = {"disp": disp, "warped": warped}
+    if return_velocities:
+        res["velocities"] = vels
+    return res
+
+
+def admm(J: torch.Tensor, r: torch.Tensor, lam: float, theta: float, order: int, iters: int,
+         data_term: int = 2, eps: float = 1e-8, ws: torch.Tensor | None = None):
+    """``iters`` ADMM iterations from zero for a given J, r.  Returns (w, b, v)."""
+    _check(r, "r")
+    shp = tuple(r.shape)
+    _check(J, "J", (3,) + shp)
+    w, b, v = (torch.empty_like(J) for _ in range(3))
+    ws = _ws(shp, ws, r.device)
+    p = params(lam, theta, order, 1, iters, data_term, eps)
+    _lib.call("nadmm_admm", dims_of(shp), ctypes.byref(p), _ptr(J), _ptr(r), _ptr(w), _ptr(b),
+              _ptr(v), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    return w, b, v
+
+
+def fourier_solve(s: torch.Tensor, lam: float, theta: float, order: int,
+                  ws: torch.Tensor | None = None) -> torch.Tensor:
+    """w = F^-1[theta F(s) / (theta + lam K^order)] per component."""
+    _check(s, "s")
+    shp = tuple(s.shape[1:])
+    _check(s, "s", (3,) + shp)
+    w = torch.empty_like(s)
+    ws = _ws(shp, ws, s.device)
+    p = params(lam, theta, order)
+    _lib.call("nadmm_fourier_solve", dims_of(shp), ctypes.byref(p), _ptr(s), _ptr(w), _ptr(ws),
+              ctypes.c_size_t(ws.numel()), _stream())
+    return w
+
+
+def warp(img: torch.Tensor, disp: torch.Tensor, ref: torch.Tensor | None = None,
+         grad: bool = False):
+    """Returns (warped, grad or None, resid or None)."""
+    _check(img, "img")
+    shp = tuple(img.shape)
+    _check(disp, "disp", (3,) + shp)
+    if ref is not None:
+        _check(ref, "ref", shp)
+    out = torch.empty_like(img)
+    g = torch.empty_like(disp) if grad else None
+    rs = torch.empty_like(img) if ref is not None else None
+    _lib.call("nadmm_warp", dims_of(shp), _ptr(img), _ptr(disp), _ptr(ref), _ptr(out), _ptr(g),
+              _ptr(rs), _stream())
+    return out, g, rs
+
+
+def compose(u: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+    """Displacement of (Id + u) o (Id + v): v(x) + u(x + v(x))."""
+    _check(u, "u")
+    _check(v, "v", tuple(u.shape))
+    out = torch.empty_like(u)
+    _lib.call("nadmm_compose", dims_of(u.shape), _ptr(u), _ptr(v), _ptr(out), _stream())
+    return out
+
+
+def expmap(vel: torch.Tensor, steps: int, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Scaling and squaring with ``steps`` squarings."""
+    _check(vel, "vel")
+    shp = tuple(vel.shape[1:])
+    out = torch.empty_like(vel)
+    ws = _ws(shp, ws, vel.device)
+    _lib.call("nadmm_expmap", dims_of(shp), _ptr(vel), ctypes.c_int32(steps), _ptr(out), _ptr(ws),
+              ctypes.c_size_t(ws.numel()), _stream())
+    return out
+
+
+def jacobian(disp: torch.Tensor, want_det: bool = False, ws: torch.Tensor | None = None):
+    """Returns (stats, n_nonpos, det): stats = float64 [min, max, mean] of
+    det(I + D disp), n_nonpos = int64 [count of det <= 0], det optional."""
+    _check(disp, "disp")
+    shp = tuple(disp.shape[1:])
+    det = torch.empty(shp, dtype=torch.float32, device=disp.device) if want_det else None
+    stats = torch.empty(3, dtype=torch.float64, device=disp.device)
+    nneg = torch.empty(1, dtype=torch.int64, device=disp.device)
+    ws = _ws(shp, ws, disp.device)
+    _lib.call("nadmm_jacobian", dims_of(shp), _ptr(disp), _ptr(det), _ptr(stats), _ptr(nneg),
+              _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    return stats, nneg, det

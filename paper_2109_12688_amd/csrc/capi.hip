@@ -1,0 +1,480 @@
+// C ABI of the registration library: argument validation, workspace layout
+// and the host-side loop orchestration (Sec. 2 iterative scheme, Sec. 3
+// Eq. (5) recurrence).  All device work is enqueued on the caller's stream;
+// nothing here synchronises or allocates device memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/nadmm.h"
+#include "kernels.h"
+
+using namespace nadmm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+nadmm_status fail(nadmm_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(NADMM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- optional per-kernel event timing -----------------------------------
+enum KernelKind {
+  KK_FILL, KK_SCALE, KK_WARP, KK_GRAD, KK_ADMM_INIT, KK_PASS_A, KK_PASS_B, KK_PASS_C_OUT,
+  KK_PASS_C_ITER, KK_PASS_C_WB, KK_PASS_C_COMPOSE, KK_COMPOSE, KK_JACOBIAN, KK_COUNT
+};
+const char* const kKindNames[KK_COUNT] = {
+    "fill", "scale", "warp", "grad_resid", "admm_init", "pass_a_fwd_x", "pass_b_yz_solve",
+    "pass_c_out", "pass_c_iter", "pass_c_final_wb", "pass_c_compose", "compose", "jacobian"};
+
+struct ProfRecord {
+  int kind;
+  hipEvent_t start, stop;
+};
+bool g_prof = false;
+std::vector<ProfRecord> g_records;
+std::vector<hipEvent_t> g_free_events;
+
+hipEvent_t take_event() {
+  if (!g_free_events.empty()) {
+    hipEvent_t e = g_free_events.back();
+    g_free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs launch() and, when timing is on, brackets it with events on st.
+template <class F>
+hipError_t timed(int kind, hipStream_t st, F&& launch) {
+  if (!g_prof) return launch();
+  ProfRecord r{kind, take_event(), take_event()};
+  if (!r.start || !r.stop) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(r.start, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(r.stop, st);
+  if (e != hipSuccess) return e;
+  g_records.push_back(r);
+  return hipSuccess;
+}
+
+bool fft_length_ok(int n) {
+  if (n < 4 || n > 256) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+nadmm_status check_dims(const nadmm_dims& d) {
+  if (!fft_length_ok(d.nx) || !fft_length_ok(d.ny) || !fft_length_ok(d.nz))
+    return fail(NADMM_ERR_UNSUPPORTED_SIZE,
+                "dims (%d, %d, %d): each must be 2^a 3^b in [4, 256]", d.nx, d.ny, d.nz);
+  if (d.nx % 2 || d.ny % 2)
+    return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d): nx and ny must be even", d.nx,
+                d.ny, d.nz);
+  if (d.ny * d.nz > 16384)
+    return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d): ny*nz must be <= 16384", d.nx,
+                d.ny, d.nz);
+  return NADMM_OK;
+}
+
+nadmm_status check_params(const nadmm_params* p, bool need_outer) {
+  if (!p) return fail(NADMM_ERR_INVALID_ARG, "params is NULL");
+  if (!(isfinite(p->theta) && p->theta > 0))
+    return fail(NADMM_ERR_INVALID_ARG, "theta must be finite and > 0 (got %g)", p->theta);
+  if (!(isfinite(p->lambda) && p->lambda >= 0))
+    return fail(NADMM_ERR_INVALID_ARG, "lambda must be finite and >= 0 (got %g)", p->lambda);
+  if (p->order < 1 || p->order > 4)
+    return fail(NADMM_ERR_INVALID_ARG, "order must be in [1, 4] (got %d)", p->order);
+  if (p->data_term != 1 && p->data_term != 2)
+    return fail(NADMM_ERR_INVALID_ARG, "data_term must be 1 or 2 (got %d)", p->data_term);
+  if (p->data_term == 1 && !(isfinite(p->eps) && p->eps > 0))
+    return fail(NADMM_ERR_INVALID_ARG, "eps must be finite and > 0 for data_term 1");
+  if (p->iters < 1 || p->iters > 100000)
+    return fail(NADMM_ERR_INVALID_ARG, "iters must be in [1, 100000] (got %d)", p->iters);
+  if (need_outer && (p->outer < 0 || p->outer > 100000))
+    return fail(NADMM_ERR_INVALID_ARG, "outer must be in [0, 100000] (got %d)", p->outer);
+  return NADMM_OK;
+}
+
+nadmm_status check_ptr(const void* p, const char* name, bool nullable) {
+  if (!p) return nullable ? NADMM_OK : fail(NADMM_ERR_INVALID_ARG, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(p) & 15)
+    return fail(NADMM_ERR_INVALID_ARG, "%s is not 16-byte aligned", name);
+  return NADMM_OK;
+}
+
+#define CHECK(expr)                         \
+  do {                                      \
+    nadmm_status s_ = (expr);               \
+    if (s_ != NADMM_OK) return s_;          \
+  } while (0)
+
+// Workspace: 17 float32 fields of V values (each region 256-byte aligned)
+// plus the Jacobian partials.
+struct Layout {
+  size_t J, r, iw, s1, s2, X, u, jac, total;
+};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+Layout layout(const nadmm_dims& d) {
+  const size_t V = (size_t)d.nx * d.ny * d.nz;
+  const size_t f3 = align256(3 * V * sizeof(float)), f1 = align256(V * sizeof(float));
+  Layout L;
+  size_t o = 0;
+  L.J = o; o += f3;
+  L.r = o; o += f1;
+  L.iw = o; o += f1;
+  L.s1 = o; o += f3;
+  L.s2 = o; o += f3;
+  L.X = o; o += f3;
+  L.u = o; o += f3;
+  L.jac = o; o += align256(kJacBlocks * 4 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+nadmm_status check_ws(const nadmm_dims& d, void* ws, size_t bytes) {
+  CHECK(check_ptr(ws, "workspace", false));
+  const size_t need = layout(d).total;
+  if (bytes < need)
+    return fail(NADMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                bytes, need);
+  return NADMM_OK;
+}
+
+Geo geo(const nadmm_dims& d) { return Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}; }
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// gamma_k = (alpha^k - 1) / alpha^{k+1}, alpha^0 = 1 (Eq. (5)), float64.
+std::vector<double> nesterov_gammas(int n) {
+  std::vector<double> g(n > 0 ? n : 0);
+  double a = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const double an = (1.0 + sqrt(1.0 + 4.0 * a * a)) / 2.0;
+    g[k] = (a - 1.0) / an;
+    a = an;
+  }
+  return g;
+}
+
+struct Plans {
+  FftPlan x, y, z;
+};
+
+Plans plans(const nadmm_dims& d) { return Plans{make_plan(d.nx), make_plan(d.ny), make_plan(d.nz)}; }
+
+// One application of the w-step operator S to t = s1 + gamma (s1 - s2)
+// through passes A and B; pass C (with its mode) is issued by the caller.
+hipError_t spectral_ab(const Geo& g, const Plans& pl, const nadmm_params* p, const float* s1,
+                       const float* s2, float gamma, float2* X, hipStream_t st) {
+  hipError_t e = timed(KK_PASS_A, st, [&] { return launch_pass_a(g, pl.x, s1, s2, gamma, X, st); });
+  if (e != hipSuccess) return e;
+  return timed(KK_PASS_B, st, [&] {
+    return launch_pass_b(g, pl.y, pl.z, X, (float)p->lambda, (float)p->theta, p->order, st);
+  });
+}
+
+// The ADMM loop of one warping, in the two-field form: s^0 already in S1.
+// Runs iterations k = 1 .. iters-1 and leaves s^{iters-1} in *cur.
+nadmm_status admm_iterations(const Geo& g, const Plans& pl, const nadmm_params* p,
+                             const float* J, const float* r, float*& cur, float*& prev,
+                             float2* X, float* v_last, hipStream_t st) {
+  const std::vector<double> gam = nesterov_gammas(p->iters);
+  for (int k = 1; k < p->iters; ++k) {
+    const float gk = (float)gam[k - 1];
+    const float* s2 = (k == 1) ? nullptr : prev;  // gamma_0 = 0: s^{-1} never read
+    HIP_TRY(spectral_ab(g, pl, p, cur, s2, gk, X, st));
+    PassCArgs a{};
+    a.X = X;
+    a.s1 = cur;
+    a.s2 = s2;
+    a.gamma = gk;
+    a.J = J;
+    a.r = r;
+    a.theta = (float)p->theta;
+    a.eps = (float)p->eps;
+    a.data_term = p->data_term;
+    a.out = prev;  // s^k overwrites s^{k-2} voxel by voxel
+    a.v_out = (k == p->iters - 1) ? v_last : nullptr;
+    HIP_TRY(timed(KK_PASS_C_ITER, st, [&] { return launch_pass_c(g, pl.x, kIter, a, st); }));
+    float* tmp = cur;
+    cur = prev;
+    prev = tmp;
+  }
+  return NADMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nadmm_abi_version(void) { return NADMM_ABI_VERSION; }
+
+const char* nadmm_status_string(nadmm_status s) {
+  switch (s) {
+    case NADMM_OK: return "NADMM_OK";
+    case NADMM_ERR_INVALID_ARG: return "NADMM_ERR_INVALID_ARG";
+    case NADMM_ERR_UNSUPPORTED_SIZE: return "NADMM_ERR_UNSUPPORTED_SIZE";
+    case NADMM_ERR_WORKSPACE: return "NADMM_ERR_WORKSPACE";
+    case NADMM_ERR_HIP: return "NADMM_ERR_HIP";
+  }
+  return "NADMM_ERR_UNKNOWN";
+}
+
+const char* nadmm_last_error(void) { return g_err; }
+
+nadmm_status nadmm_workspace_size(nadmm_dims d, const nadmm_params* p, size_t* bytes) {
+  (void)p;
+  if (!bytes) return fail(NADMM_ERR_INVALID_ARG, "bytes is NULL");
+  CHECK(check_dims(d));
+  *bytes = layout(d).total;
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p, const float* fixed,
+                            const float* moving, const float* init_disp, float* disp,
+                            float* warped, float* velocities, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_params(p, true));
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(init_disp, "init_disp", true));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(warped, "warped", true));
+  CHECK(check_ptr(velocities, "velocities", true));
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  const Geo g = geo(d);
+  const Plans pl = plans(d);
+  const Layout L = layout(d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t V = (size_t)g.V;
+  float* J = at<float>(workspace, L.J);
+  float* r = at<float>(workspace, L.r);
+  float* iw = at<float>(workspace, L.iw);
+  float* S1 = at<float>(workspace, L.s1);
+  float* S2 = at<float>(workspace, L.s2);
+  float2* X = at<float2>(workspace, L.X);
+  float* U = at<float>(workspace, L.u);
+
+  // Displacement buffers alternate between U and disp so that the last
+  // warping writes disp.
+  auto dst_of = [&](int c) { return ((p->outer - 1 - c) % 2 == 0) ? disp : U; };
+  const float* u_src;
+  if (init_disp) {
+    u_src = init_disp;
+  } else {
+    float* z = (p->outer > 0 && dst_of(0) == disp) ? U : disp;
+    HIP_TRY(timed(KK_FILL, st, [&] { return launch_fill(z, 0.0f, 3 * V, st); }));
+    u_src = z;
+  }
+  if (p->outer == 0) {
+    if (u_src != disp) HIP_TRY(hipMemcpyAsync(disp, u_src, 3 * V * sizeof(float),
+                                              hipMemcpyDeviceToDevice, st));
+    if (warped) HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, disp, warped, st); }));
+    return NADMM_OK;
+  }
+  HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, u_src, iw, st); }));
+  for (int c = 0; c < p->outer; ++c) {
+    const bool last = (c == p->outer - 1);
+    // linearised data term at the current warp, and s^0 (Eq. (6) from zero)
+    HIP_TRY(timed(KK_GRAD, st, [&] { return launch_grad_resid(g, iw, fixed, J, r, S1, (float)p->theta, (float)p->eps,
+                              p->data_term, st); }));
+    float* cur = S1;
+    float* prev = S2;
+    CHECK(admm_iterations(g, pl, p, J, r, cur, prev, X, nullptr, st));
+    // final w = S s^{K-1}, composed onto the displacement
+    HIP_TRY(spectral_ab(g, pl, p, cur, nullptr, 0.0f, X, st));
+    PassCArgs a{};
+    a.X = X;
+    a.out = dst_of(c);
+    a.u_old = u_src;
+    a.img = moving;
+    a.iw_out = last ? warped : iw;
+    a.vel_out = velocities ? velocities + (size_t)c * 3 * V : nullptr;
+    HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_pass_c(g, pl.x, kCompose, a, st); }));
+    u_src = a.out;
+  }
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_admm(nadmm_dims d, const nadmm_params* p, const float* J, const float* r,
+                        float* w_out, float* b_out, float* v_out, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_params(p, false));
+  CHECK(check_ptr(J, "J", false));
+  CHECK(check_ptr(r, "r", false));
+  CHECK(check_ptr(w_out, "w_out", false));
+  CHECK(check_ptr(b_out, "b_out", true));
+  CHECK(check_ptr(v_out, "v_out", true));
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  const Geo g = geo(d);
+  const Plans pl = plans(d);
+  const Layout L = layout(d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* S1 = at<float>(workspace, L.s1);
+  float* S2 = at<float>(workspace, L.s2);
+  float2* X = at<float2>(workspace, L.X);
+  HIP_TRY(timed(KK_ADMM_INIT, st, [&] { return launch_admm_init(g, J, r, S1, p->iters == 1 ? v_out : nullptr, (float)p->theta,
+                           (float)p->eps, p->data_term, st); }));
+  float* cur = S1;
+  float* prev = S2;
+  CHECK(admm_iterations(g, pl, p, J, r, cur, prev, X, v_out, st));
+  HIP_TRY(spectral_ab(g, pl, p, cur, nullptr, 0.0f, X, st));
+  PassCArgs a{};
+  a.X = X;
+  a.s1 = cur;
+  a.out = w_out;
+  a.b_out = b_out;
+  HIP_TRY(timed(KK_PASS_C_WB, st, [&] { return launch_pass_c(g, pl.x, kFinalWB, a, st); }));
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_fourier_solve(nadmm_dims d, const nadmm_params* p, const float* s, float* w,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_params(p, false));
+  CHECK(check_ptr(s, "s", false));
+  CHECK(check_ptr(w, "w", false));
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  const Geo g = geo(d);
+  const Plans pl = plans(d);
+  const Layout L = layout(d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float2* X = at<float2>(workspace, L.X);
+  HIP_TRY(spectral_ab(g, pl, p, s, nullptr, 0.0f, X, st));
+  PassCArgs a{};
+  a.X = X;
+  a.out = w;
+  HIP_TRY(timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c(g, pl.x, kOutY, a, st); }));
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_warp(nadmm_dims d, const float* img, const float* disp, const float* ref,
+                        float* out, float* grad, float* resid, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_ptr(img, "img", false));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(ref, "ref", true));
+  CHECK(check_ptr(out, "out", false));
+  CHECK(check_ptr(grad, "grad", true));
+  CHECK(check_ptr(resid, "resid", true));
+  if (resid && !ref) return fail(NADMM_ERR_INVALID_ARG, "resid requires ref");
+  if (out == img || out == disp) return fail(NADMM_ERR_INVALID_ARG, "out aliases an input");
+  const Geo g = geo(d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, img, disp, out, st); }));
+  if (grad || resid)
+    HIP_TRY(timed(KK_GRAD, st, [&] { return launch_grad_resid(g, out, resid ? ref : nullptr, grad, resid, nullptr, 1.0f, 1.0f, 2,
+                              st); }));
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_compose(nadmm_dims d, const float* u, const float* v, float* out,
+                           void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_ptr(u, "u", false));
+  CHECK(check_ptr(v, "v", false));
+  CHECK(check_ptr(out, "out", false));
+  if (out == u || out == v) return fail(NADMM_ERR_INVALID_ARG, "out aliases an input");
+  HIP_TRY(timed(KK_COMPOSE, static_cast<hipStream_t>(stream), [&] { return launch_compose(geo(d), u, v, out, static_cast<hipStream_t>(stream)); }));
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_expmap(nadmm_dims d, const float* vel, int32_t steps, float* out,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_ptr(vel, "vel", false));
+  CHECK(check_ptr(out, "out", false));
+  if (steps < 0 || steps > 30) return fail(NADMM_ERR_INVALID_ARG, "steps must be in [0, 30]");
+  if (out == vel) return fail(NADMM_ERR_INVALID_ARG, "out aliases vel");
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  const Geo g = geo(d);
+  const Layout L = layout(d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t n = 3 * (size_t)g.V;
+  float* T = at<float>(workspace, L.u);
+  // ping-pong so that the last squaring writes out
+  float* a = (steps % 2 == 0) ? out : T;
+  float* b = (a == out) ? T : out;
+  HIP_TRY(timed(KK_SCALE, st, [&] { return launch_scale(vel, a, (float)ldexp(1.0, -steps), n, st); }));
+  for (int k = 0; k < steps; ++k) {
+    HIP_TRY(timed(KK_COMPOSE, st, [&] { return launch_compose(g, a, a, b, st); }));
+    float* t = a;
+    a = b;
+    b = t;
+  }
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_jacobian(nadmm_dims d, const float* disp, float* det, double* stats,
+                            int64_t* n_nonpos, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(det, "det", true));
+  CHECK(check_ptr(stats, "stats", false));
+  CHECK(check_ptr(n_nonpos, "n_nonpos", false));
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  const Layout L = layout(d);
+  HIP_TRY(timed(KK_JACOBIAN, static_cast<hipStream_t>(stream), [&] { return launch_jacobian(geo(d), disp, det, at<double>(workspace, L.jac), stats, n_nonpos,
+                          static_cast<hipStream_t>(stream)); }));
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_profile_enable(int enable) {
+  g_prof = enable != 0;
+  return NADMM_OK;
+}
+
+int nadmm_profile_read(int max, const char** names, int64_t* counts, double* total_ms) {
+  int64_t cnt[KK_COUNT] = {0};
+  double ms[KK_COUNT] = {0};
+  int status = KK_COUNT;
+  for (const ProfRecord& r : g_records) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) {
+      status = -1;
+    } else {
+      cnt[r.kind] += 1;
+      ms[r.kind] += t;
+    }
+    g_free_events.push_back(r.start);
+    g_free_events.push_back(r.stop);
+  }
+  g_records.clear();
+  for (int k = 0; k < KK_COUNT && k < max; ++k) {
+    if (names) names[k] = kKindNames[k];
+    if (counts) counts[k] = cnt[k];
+    if (total_ms) total_ms[k] = ms[k];
+  }
+  if (status < 0) fail(NADMM_ERR_HIP, "event synchronisation failed while reading timings");
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Internal launch interface of the gfx950 kernels (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_lds.h"
+
+namespace nadmm {
+
+struct Geo {
+  int nx, ny, nz;
+  int V;  // nx * ny * nz
+};
+
+// Rows of the y axis handled by one x-line workgroup (even, divides ny).
+int xline_rows(int ny);
+// Threads of the x-line passes and of the y-z plane pass for these sizes.
+int xline_threads(const Geo& g);
+int plane_threads(const Geo& g);
+// Elements-per-thread bound every LDS FFT stage is compiled for.
+constexpr int kEpt = 16;
+constexpr int kJacBlocks = 1024;
+
+FftPlan make_plan(int n);
+
+// Pass C (inverse x transform + pointwise update) output modes.
+enum PassCMode { kOutY = 0, kIter = 1, kFinalWB = 2, kCompose = 3 };
+
+struct PassCArgs {
+  const float2* X;
+  const float* s1;   // s^{k-1} (iteration), s (final)
+  const float* s2;   // s^{k-2} or nullptr when gamma = 0
+  float gamma;
+  const float* J;
+  const float* r;
+  float theta;
+  float eps;
+  int data_term;
+  float* out;        // kOutY: y; kIter: s^k (may alias s2); kFinalWB: w; kCompose: new u
+  float* v_out;      // kIter: optional v^k
+  float* b_out;      // kFinalWB: optional b
+  const float* u_old;  // kCompose: displacement before this warping
+  const float* img;    // kCompose: moving image
+  float* iw_out;       // kCompose: optional moving(x + u_new(x))
+  float* vel_out;      // kCompose: optional velocity of this warping
+};
+
+hipError_t launch_fill(float* p, float value, size_t n, hipStream_t st);
+hipError_t launch_scale(const float* in, float* out, float s, size_t n, hipStream_t st);
+hipError_t launch_warp(const Geo& g, const float* img, const float* disp, float* out, hipStream_t st);
+// grad (3V, optional), resid (optional, needs ref), s0 (3V, optional: the
+// first ADMM iterate v^0 = b^0-free data step from zero, needs ref).
+hipError_t launch_grad_resid(const Geo& g, const float* iw, const float* ref, float* grad,
+                             float* resid, float* s0, float theta, float eps, int data_term,
+                             hipStream_t st);
+hipError_t launch_admm_init(const Geo& g, const float* J, const float* r, float* s0, float* v_out,
+                            float theta, float eps, int data_term, hipStream_t st);
+hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const float* s1, const float* s2,
+                         float gamma, float2* X, hipStream_t st);
+hipError_t launch_pass_b(const Geo& g, const FftPlan& py, const FftPlan& pz, float2* X,
+                         float lambda, float theta, int order, hipStream_t st);
+hipError_t launch_pass_c(const Geo& g, const FftPlan& px, PassCMode mode, const PassCArgs& a,
+                         hipStream_t st);
+hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out, hipStream_t st);
+hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* partial,
+                           double* stats, int64_t* n_nonpos, hipStream_t st);
+
+}  // namespace nadmm
