@@ -25,7 +25,7 @@
  *           anything, so a call that returns an error has enqueued nothing.
  *           HIP runtime failures return NADMM_ERR_HIP.  nadmm_last_error()
  *           gives a per-thread message for the last non-OK status.
- * Sizes.    nx and ny must be even; every dimension must be 2^a * 3^b with
+ * Sizes.    nx must be a multiple of 4 and ny even; every dimension must be 2^a * 3^b with
  *           4 <= n <= 256, and ny*nz <= 16384 (the y-z spectral plane must
  *           fit one compute unit's local memory).  Other sizes return
  *           NADMM_ERR_UNSUPPORTED_SIZE.
@@ -166,6 +166,17 @@ nadmm_status nadmm_jacobian(nadmm_dims d, const float* disp, float* det, double*
  * the records and returns the number of kinds (or -1 on a HIP failure). */
 nadmm_status nadmm_profile_enable(int enable);
 int nadmm_profile_read(int max, const char** names, int64_t* counts, double* total_ms);
+
+/* Benchmark replay of one kernel of the ADMM iteration: launches it `reps`
+ * times back to back (1 <= reps <= 10000) on the buffers that a preceding
+ * nadmm_register call with the same dims and params left in `workspace`,
+ * between two HIP events on `stream`, waits for them and writes the mean
+ * milliseconds per launch to host *avg_ms.  kind: 0 = forward x pass with
+ * extrapolation, 1 = y-z spectral pass, 2 = inverse x pass with the data
+ * step.  The replayed launches overwrite the workspace's iteration state. */
+nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t kind, int32_t reps,
+                                  void* workspace, size_t workspace_bytes, void* stream,
+                                  double* avg_ms);
 
 #ifdef __cplusplus
 }

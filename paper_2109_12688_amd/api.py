@@ -176,3 +176,17 @@ def jacobian(disp: torch.Tensor, want_det: bool = False, ws: torch.Tensor | None
     _lib.call("nadmm_jacobian", dims_of(shp), _ptr(disp), _ptr(det), _ptr(stats), _ptr(nneg),
               _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
     return stats, nneg, det
+
+
+REPLAY_KINDS = {"pass_a_fwd_x": 0, "pass_b_yz_solve": 1, "pass_c_iter": 2}
+
+
+def profile_replay(vol_shape, kind: str, reps: int, lam: float, theta: float, order: int,
+                   ws: torch.Tensor, data_term: int = 2, eps: float = 1e-8) -> float:
+    """Mean milliseconds of one iteration kernel replayed ``reps`` times back to
+    back on the state a preceding register() call left in ``ws``."""
+    p = params(lam, theta, order, 1, 2, data_term, eps)
+    ms = ctypes.c_double(0.0)
+    _lib.call("nadmm_profile_replay", dims_of(vol_shape), ctypes.byref(p), ctypes.c_int32(REPLAY_KINDS[kind]),
+              ctypes.c_int32(reps), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(), ctypes.byref(ms))
+    return float(ms.value)

@@ -87,11 +87,14 @@ nadmm_status check_dims(const nadmm_dims& d) {
   if (!fft_length_ok(d.nx) || !fft_length_ok(d.ny) || !fft_length_ok(d.nz))
     return fail(NADMM_ERR_UNSUPPORTED_SIZE,
                 "dims (%d, %d, %d): each must be 2^a 3^b in [4, 256]", d.nx, d.ny, d.nz);
-  if (d.nx % 2 || d.ny % 2)
-    return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d): nx and ny must be even", d.nx,
-                d.ny, d.nz);
+  if (d.nx % 4 || d.ny % 2)
+    return fail(NADMM_ERR_UNSUPPORTED_SIZE,
+                "dims (%d, %d, %d): nx must be a multiple of 4 and ny even", d.nx, d.ny, d.nz);
   if (d.ny * d.nz > 16384)
     return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d): ny*nz must be <= 16384", d.nx,
+                d.ny, d.nz);
+  if (!launch_shape_ok(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}))
+    return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d): no valid launch shape", d.nx,
                 d.ny, d.nz);
   return NADMM_OK;
 }
@@ -444,6 +447,59 @@ nadmm_status nadmm_jacobian(nadmm_dims d, const float* disp, float* det, double*
   const Layout L = layout(d);
   HIP_TRY(timed(KK_JACOBIAN, static_cast<hipStream_t>(stream), [&] { return launch_jacobian(geo(d), disp, det, at<double>(workspace, L.jac), stats, n_nonpos,
                           static_cast<hipStream_t>(stream)); }));
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t kind, int32_t reps,
+                                  void* workspace, size_t workspace_bytes, void* stream,
+                                  double* avg_ms) {
+  CHECK(check_dims(d));
+  CHECK(check_params(p, false));
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  if (!avg_ms) return fail(NADMM_ERR_INVALID_ARG, "avg_ms is NULL");
+  if (kind < 0 || kind > 2) return fail(NADMM_ERR_INVALID_ARG, "kind must be 0, 1 or 2");
+  if (reps < 1 || reps > 10000) return fail(NADMM_ERR_INVALID_ARG, "reps must be in [1, 10000]");
+  const Geo g = geo(d);
+  const Plans pl = plans(d);
+  const Layout L = layout(d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* J = at<float>(workspace, L.J);
+  float* r = at<float>(workspace, L.r);
+  float* S1 = at<float>(workspace, L.s1);
+  float* S2 = at<float>(workspace, L.s2);
+  float2* X = at<float2>(workspace, L.X);
+  const float gamma = (float)nesterov_gammas(3)[2];
+  PassCArgs a{};
+  a.X = X;
+  a.s1 = S1;
+  a.s2 = S2;
+  a.gamma = gamma;
+  a.J = J;
+  a.r = r;
+  a.theta = (float)p->theta;
+  a.eps = (float)p->eps;
+  a.data_term = p->data_term;
+  a.out = S2;
+  auto launch = [&]() -> hipError_t {
+    if (kind == 0) return launch_pass_a(g, pl.x, S1, S2, gamma, X, st);
+    if (kind == 1)
+      return launch_pass_b(g, pl.y, pl.z, X, (float)p->lambda, (float)p->theta, p->order, st);
+    return launch_pass_c(g, pl.x, kIter, a, st);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t err = hipEventCreate(&e1);
+  if (err == hipSuccess) err = launch();  // warm the caches once
+  if (err == hipSuccess) err = hipEventRecord(e0, st);
+  for (int i = 0; i < reps && err == hipSuccess; ++i) err = launch();
+  if (err == hipSuccess) err = hipEventRecord(e1, st);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(NADMM_ERR_HIP, "replay: %s", hipGetErrorString(err));
+  *avg_ms = (double)ms / reps;
   return NADMM_OK;
 }
 

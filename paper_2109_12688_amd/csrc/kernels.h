@@ -23,6 +23,22 @@ constexpr int kJacBlocks = 1024;
 
 FftPlan make_plan(int n);
 
+// Host-precomputed divisors of the x-line and y-z plane index maps.
+struct XDivs {
+  FastDiv q4;     // nx / 4 (float4 groups per row)
+  FastDiv yb;     // rows per x-line workgroup
+  FastDiv yb2;    // row pairs per workgroup
+  FastDiv nh;     // nx / 2 (packed half-spectrum length)
+  FastDiv lines;  // complex lines per x-line workgroup: 3 * yb / 2
+  FastDiv ny, nz;
+};
+XDivs make_xdivs(const Geo& g);
+// True when every kernel's compile-time per-thread bounds hold for these sizes.
+bool launch_shape_ok(const Geo& g);
+// Per-thread item bounds the batched loads are compiled for (checked on the host).
+constexpr int kXItems = 4;   // float4 groups per thread in the x-line passes
+constexpr int kPItems = 8;   // float4 (two complex) per thread in the plane pass
+
 // Pass C (inverse x transform + pointwise update) output modes.
 enum PassCMode { kOutY = 0, kIter = 1, kFinalWB = 2, kCompose = 3 };
 

@@ -56,19 +56,71 @@ int plane_threads(const Geo& g) {
   return t;
 }
 
+// Fewest Stockham stages for n, radices from {16, 12, 8, 6, 4, 3, 2}; among
+// plans with equally few stages the one with the largest leading radices.
+static bool plan_search(int m, int depth, int* out) {
+  static const int radices[7] = {16, 12, 8, 6, 4, 3, 2};
+  if (m == 1) return depth == 0;
+  if (depth == 0) return false;
+  for (int i = 0; i < 7; ++i) {
+    if (m % radices[i] == 0 && plan_search(m / radices[i], depth - 1, out + 1)) {
+      out[0] = radices[i];
+      return true;
+    }
+  }
+  return false;
+}
+
 FftPlan make_plan(int n) {
   FftPlan p{};
   p.n = n;
-  int m = n;
-  const int radices[4] = {8, 4, 3, 2};
-  for (int i = 0; i < 4; ++i) {
-    while (m % radices[i] == 0 && m > 1 && p.nstages < 8) {
-      p.radix[p.nstages++] = radices[i];
-      m /= radices[i];
+  p.nstages = -1;
+  int rad[8] = {0};
+  for (int depth = 1; depth <= 8; ++depth) {
+    if (plan_search(n, depth, rad)) {
+      p.nstages = depth;
+      break;
     }
   }
-  if (m != 1) p.nstages = -1;
+  int ns = 1;
+  for (int i = 0; i < p.nstages; ++i) {
+    FftStage& s = p.st[i];
+    s.R = rad[i];
+    s.Ns = ns;
+    s.nb = n / s.R;
+    s.twstride = n / (ns * s.R);
+    s.div_nb = make_fastdiv(s.nb);
+    s.div_ns = make_fastdiv(ns);
+    ns *= s.R;
+  }
   return p;
+}
+
+bool launch_shape_ok(const Geo& g) {
+  if (g.nx % 4 || g.ny % 2) return false;
+  const int yb = xline_rows(g.ny), xt = xline_threads(g), pt = plane_threads(g);
+  const FftPlan px = make_plan(g.nx), py = make_plan(g.ny), pz = make_plan(g.nz);
+  if (px.nstages < 1 || py.nstages < 1 || pz.nstages < 1) return false;
+  const bool fft_a = 3 * (yb / 2) * g.nx <= kEpt * xt;       // x-line FFT elements per thread
+  const bool load_a = 3 * yb * (g.nx / 4) <= kXItems * xt;    // pass A float4 loads
+  const bool point_c = yb * (g.nx / 4) <= 2 * xt;             // pass C float4 runs
+  const bool fft_b = g.ny * g.nz <= kEpt * pt;                // plane FFT elements per thread
+  const bool load_b = g.ny * g.nz / 2 <= kPItems * pt;        // pass B float4 loads
+  const bool div_ok = g.ny * g.nz < 65536 && 3 * yb * g.nx < 65536;  // FastDiv range
+  return fft_a && load_a && point_c && fft_b && load_b && div_ok;
+}
+
+XDivs make_xdivs(const Geo& g) {
+  const int yb = xline_rows(g.ny);
+  XDivs d;
+  d.q4 = make_fastdiv(g.nx / 4);
+  d.yb = make_fastdiv(yb);
+  d.yb2 = make_fastdiv(yb / 2);
+  d.nh = make_fastdiv(g.nx / 2);
+  d.lines = make_fastdiv(3 * (yb / 2));
+  d.ny = make_fastdiv(g.ny);
+  d.nz = make_fastdiv(g.nz);
+  return d;
 }
 
 // ---------------------------------------------------------------------------
@@ -283,40 +335,71 @@ hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* o
 // X layout: X[((c * nx/2 + p) * nz + z) * ny + y], p < nx/2; p = 0 holds
 // (DC, Nyquist) of the real row as one complex value.
 // ---------------------------------------------------------------------------
-__global__ void k_pass_a(Geo g, FftPlan px, int yb, const float* __restrict__ s1,
-                         const float* __restrict__ s2, float gamma, float2* __restrict__ X) {
+__global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd,
+                                                const float* __restrict__ s1,
+                                                const float* __restrict__ s2, float gamma,
+                                                float2* __restrict__ X) {
   extern __shared__ float2 lds[];
-  const int nx = g.nx, nh = g.nx / 2;
-  const int ls = nx + 1;           // padded line stride (complex)
-  const int lines = 3 * (yb / 2);  // complex lines: (component, row pair)
+  const int nx = g.nx, nh = g.nx / 2, q4 = g.nx / 4;
+  const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
+  const int ls = nx + 1;  // padded line stride (complex)
   float2* tw = lds;
   float2* buf = lds + nx;
   const int y0 = blockIdx.x * yb, z = blockIdx.y;
+  const int nthr = blockDim.x;
   make_twiddles(tw, nx);
 
-  // load t = s1 + gamma (s1 - s2) and pack rows 2q, 2q+1 as re/im
+  // load t = s1 + gamma (s1 - s2) as float4 runs along x (all loads first)
+  const int items = 3 * yb * q4;
+  float4 va[kXItems], vb[kXItems];
+  int goff[kXItems];
+#pragma unroll
+  for (int it = 0; it < kXItems; ++it) {
+    const int idx = threadIdx.x + it * nthr;
+    if (idx < items) {
+      const int row = (int)fdiv((uint32_t)idx, xd.q4);
+      const int x4 = idx - row * q4;
+      const int c = (int)fdiv((uint32_t)row, xd.yb);
+      const int yy = row - c * yb;
+      goff[it] = c * g.V + (z * g.ny + y0 + yy) * nx + 4 * x4;
+      va[it] = *reinterpret_cast<const float4*>(s1 + goff[it]);
+      if (s2) vb[it] = *reinterpret_cast<const float4*>(s2 + goff[it]);
+    }
+  }
   float* bf = reinterpret_cast<float*>(buf);
-  const int nvox = 3 * yb * nx;
-  for (int idx = threadIdx.x; idx < nvox; idx += blockDim.x) {
-    const int c = idx / (yb * nx);
-    const int rem = idx - c * yb * nx;
-    const int yy = rem / nx, x = rem - yy * nx;
-    const int gi = c * g.V + (z * g.ny + y0 + yy) * nx + x;
-    float t = s1[gi];
-    if (s2) t = fmaf(gamma, t - s2[gi], t);
-    const int line = c * (yb / 2) + (yy >> 1);
-    bf[2 * (line * ls + x) + (yy & 1)] = t;
+#pragma unroll
+  for (int it = 0; it < kXItems; ++it) {
+    const int idx = threadIdx.x + it * nthr;
+    if (idx < items) {
+      const int row = (int)fdiv((uint32_t)idx, xd.q4);
+      const int x4 = idx - row * q4;
+      const int c = (int)fdiv((uint32_t)row, xd.yb);
+      const int yy = row - c * yb;
+      float4 t = va[it];
+      if (s2) {
+        const float4 u = vb[it];
+        t = make_float4(fmaf(gamma, t.x - u.x, t.x), fmaf(gamma, t.y - u.y, t.y),
+                        fmaf(gamma, t.z - u.z, t.z), fmaf(gamma, t.w - u.w, t.w));
+      }
+      const int line = c * yb2 + (yy >> 1);
+      float* d = bf + 2 * (line * ls + 4 * x4) + (yy & 1);
+      d[0] = t.x;
+      d[2] = t.y;
+      d[4] = t.z;
+      d[6] = t.w;
+    }
   }
   __syncthreads();
-  fft_lines<kEpt, false, true>(buf, tw, px, lines, 1, ls);
+  fft_lines<kEpt, false>(buf, tw, px, xd.lines, 1, ls);
 
   // split into the two rows' half spectra and store (row pairs contiguous)
-  const int nout = 3 * nh * (yb / 2);
-  for (int idx = threadIdx.x; idx < nout; idx += blockDim.x) {
-    const int yp = idx % (yb / 2);
-    const int ck = idx / (yb / 2);
-    const int c = ck / nh, k = ck - c * nh;
-    const float2* Z = buf + (c * (yb / 2) + yp) * ls;
+  const int nout = 3 * nh * yb2;
+  for (int idx = threadIdx.x; idx < nout; idx += nthr) {
+    const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
+    const int yp = idx - ck * yb2;
+    const int c = (int)fdiv((uint32_t)ck, xd.nh);
+    const int k = ck - c * nh;
+    const float2* Z = buf + (c * yb2 + yp) * ls;
     float4 o;
     if (k == 0) {
       const float2 z0 = Z[0], zn = Z[nh];
@@ -341,7 +424,7 @@ hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const float* s1, const
                          float gamma, float2* X, hipStream_t st) {
   const int yb = xline_rows(g.ny);
   hipLaunchKernelGGL(k_pass_a, dim3(g.ny / yb, g.nz), dim3(xline_threads(g)), pass_a_lds(g), st,
-                     g, px, yb, s1, s2, gamma, X);
+                     g, px, make_xdivs(g), s1, s2, gamma, X);
   return hipGetLastError();
 }
 
@@ -355,11 +438,13 @@ __device__ __forceinline__ float spectral_mult(float k0, float lambda, float the
   return theta / (theta + lambda * kn) * inv_v;
 }
 
-__global__ void k_pass_b(Geo g, FftPlan py, FftPlan pz, float2* __restrict__ X, float lambda,
-                         float theta, int order) {
+__global__ void __launch_bounds__(1024) k_pass_b(Geo g, FftPlan py, FftPlan pz, XDivs xd,
+                                                 float2* __restrict__ X, float lambda, float theta,
+                                                 int order) {
   extern __shared__ float2 lds[];
   const int ny = g.ny, nz = g.nz, nh = g.nx / 2;
   const int rs = ny + 1;  // padded row stride of the [z][y] plane
+  const int nthr = blockDim.x;
   float2* twy = lds;
   float2* twz = twy + ny;
   float* sy = reinterpret_cast<float*>(twz + nz);
@@ -367,11 +452,19 @@ __global__ void k_pass_b(Geo g, FftPlan py, FftPlan pz, float2* __restrict__ X, 
   float2* buf = reinterpret_cast<float2*>(sz + nz + ((ny + nz) & 1));  // keep 8-byte alignment
   const int p = blockIdx.x, c = blockIdx.y;
   float2* plane = X + (size_t)(c * nh + p) * nz * ny;
+  const int n = ny * nz, n2 = n / 2;
 
+  // issue every global load of the plane first (two complex per float4)
+  float4 v[kPItems];
+#pragma unroll
+  for (int it = 0; it < kPItems; ++it) {
+    const int i2 = threadIdx.x + it * nthr;
+    if (i2 < n2) v[it] = reinterpret_cast<const float4*>(plane)[i2];
+  }
   make_twiddles(twy, ny);
   make_twiddles(twz, nz);
   // symbol pieces 2 - 2 cos(2 pi q / n) = 4 sin^2(pi q / n), float64 then rounded
-  for (int i = threadIdx.x; i < ny + nz; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ny + nz; i += nthr) {
     if (i < ny) {
       const double s = sinpi((double)i / ny);
       sy[i] = (float)(4.0 * s * s);
@@ -380,21 +473,26 @@ __global__ void k_pass_b(Geo g, FftPlan py, FftPlan pz, float2* __restrict__ X, 
       sz[i - ny] = (float)(4.0 * s * s);
     }
   }
-  const int n = ny * nz;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int zz = i / ny, yy = i - zz * ny;
-    buf[zz * rs + yy] = plane[i];
+#pragma unroll
+  for (int it = 0; it < kPItems; ++it) {
+    const int i2 = threadIdx.x + it * nthr;
+    if (i2 < n2) {
+      const int i = 2 * i2;
+      const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;  // ny even: same row
+      buf[zz * rs + yy] = make_float2(v[it].x, v[it].y);
+      buf[zz * rs + yy + 1] = make_float2(v[it].z, v[it].w);
+    }
   }
   __syncthreads();
-  fft_lines<kEpt, false, true>(buf, twy, py, nz, 1, rs);  // along y
-  fft_lines<kEpt, false, true>(buf, twz, pz, ny, rs, 1);  // along z
+  fft_lines<kEpt, false>(buf, twy, py, xd.nz, 1, rs);  // along y (nz lines)
+  fft_lines<kEpt, false>(buf, twz, pz, xd.ny, rs, 1);  // along z (ny lines)
 
   const float inv_v = 1.0f / (float)g.V;
   if (p > 0) {
     const double sxd = sinpi((double)p / g.nx);
     const float sx = (float)(4.0 * sxd * sxd);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int zz = i / ny, yy = i - zz * ny;
+    for (int i = threadIdx.x; i < n; i += nthr) {
+      const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
       const float m = spectral_mult(sx + sy[yy] + sz[zz], lambda, theta, order, inv_v);
       float2& e = buf[zz * rs + yy];
       e = cscale(e, m);
@@ -406,9 +504,9 @@ __global__ void k_pass_b(Geo g, FftPlan py, FftPlan pz, float2* __restrict__ X, 
     float2 res[kEpt];
 #pragma unroll
     for (int it = 0; it < kEpt; ++it) {
-      const int i = threadIdx.x + it * blockDim.x;
+      const int i = threadIdx.x + it * nthr;
       if (i < n) {
-        const int zz = i / ny, yy = i - zz * ny;
+        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
         const int zr = (zz == 0) ? 0 : nz - zz, yr = (yy == 0) ? 0 : ny - yy;
         const float2 P = buf[zz * rs + yy];
         const float2 Pt = cconj(buf[zr * rs + yr]);
@@ -421,19 +519,21 @@ __global__ void k_pass_b(Geo g, FftPlan py, FftPlan pz, float2* __restrict__ X, 
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kEpt; ++it) {
-      const int i = threadIdx.x + it * blockDim.x;
+      const int i = threadIdx.x + it * nthr;
       if (i < n) {
-        const int zz = i / ny, yy = i - zz * ny;
+        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
         buf[zz * rs + yy] = res[it];
       }
     }
     __syncthreads();
   }
-  fft_lines<kEpt, true, true>(buf, twz, pz, ny, rs, 1);
-  fft_lines<kEpt, true, true>(buf, twy, py, nz, 1, rs);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int zz = i / ny, yy = i - zz * ny;
-    plane[i] = buf[zz * rs + yy];
+  fft_lines<kEpt, true>(buf, twz, pz, xd.ny, rs, 1);
+  fft_lines<kEpt, true>(buf, twy, py, xd.nz, 1, rs);
+  for (int i2 = threadIdx.x; i2 < n2; i2 += nthr) {
+    const int i = 2 * i2;
+    const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
+    const float2 a = buf[zz * rs + yy], b = buf[zz * rs + yy + 1];
+    reinterpret_cast<float4*>(plane)[i2] = make_float4(a.x, a.y, b.x, b.y);
   }
 }
 
@@ -445,93 +545,185 @@ static size_t pass_b_lds(const Geo& g) {
 hipError_t launch_pass_b(const Geo& g, const FftPlan& py, const FftPlan& pz, float2* X,
                          float lambda, float theta, int order, hipStream_t st) {
   hipLaunchKernelGGL(k_pass_b, dim3(g.nx / 2, 3), dim3(plane_threads(g)), pass_b_lds(g), st, g,
-                     py, pz, X, lambda, theta, order);
+                     py, pz, make_xdivs(g), X, lambda, theta, order);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // pass C: packed half spectrum -> y = S t, then the mode's pointwise work
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+__device__ __forceinline__ float f4get(const float4& v, int e) {
+  return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ void f4set(float4& v, int e, float s) {
+  if (e == 0) v.x = s; else if (e == 1) v.y = s; else if (e == 2) v.z = s; else v.w = s;
+}
+
 template <int MODE>
-__global__ void k_pass_c(Geo g, FftPlan px, int yb, PassCArgs a) {
+__global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, PassCArgs a) {
   extern __shared__ float2 lds[];
-  const int nx = g.nx, nh = g.nx / 2;
+  const int nx = g.nx, nh = g.nx / 2, q4 = g.nx / 4;
+  const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   const int ls = nx + 1;
-  const int lines = 3 * (yb / 2);
+  const int nthr = blockDim.x;
   float2* tw = lds;
   float2* buf = lds + nx;
   const int y0 = blockIdx.x * yb, z = blockIdx.y;
-  make_twiddles(tw, nx);
 
   // unpack two rows' half spectra into one complex row: Z = Xa + i Xb
-  const int nin = 3 * nh * (yb / 2);
-  for (int idx = threadIdx.x; idx < nin; idx += blockDim.x) {
-    const int yp = idx % (yb / 2);
-    const int ck = idx / (yb / 2);
-    const int c = ck / nh, k = ck - c * nh;
-    const float4 in = *reinterpret_cast<const float4*>(
-        a.X + ((size_t)(c * nh + k) * g.nz + z) * g.ny + y0 + 2 * yp);
-    float2* Z = buf + (c * (yb / 2) + yp) * ls;
-    // in = (a.re, a.im, b.re, b.im)
-    if (k == 0) {
-      Z[0] = make_float2(in.x, in.z);
-      Z[nh] = make_float2(in.y, in.w);
-    } else {
-      Z[k] = make_float2(in.x - in.w, in.y + in.z);
-      Z[nx - k] = make_float2(in.x + in.w, in.z - in.y);
+  const int nin = 3 * nh * yb2;
+  float4 in[kXItems];
+#pragma unroll
+  for (int it = 0; it < kXItems; ++it) {
+    const int idx = threadIdx.x + it * nthr;
+    if (idx < nin) {
+      const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
+      const int yp = idx - ck * yb2;
+      const int c = (int)fdiv((uint32_t)ck, xd.nh);
+      const int k = ck - c * nh;
+      in[it] = *reinterpret_cast<const float4*>(a.X + ((size_t)(c * nh + k) * g.nz + z) * g.ny +
+                                                y0 + 2 * yp);
+    }
+  }
+  make_twiddles(tw, nx);
+#pragma unroll
+  for (int it = 0; it < kXItems; ++it) {
+    const int idx = threadIdx.x + it * nthr;
+    if (idx < nin) {
+      const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
+      const int yp = idx - ck * yb2;
+      const int c = (int)fdiv((uint32_t)ck, xd.nh);
+      const int k = ck - c * nh;
+      float2* Z = buf + (c * yb2 + yp) * ls;
+      const float4 q = in[it];  // (a.re, a.im, b.re, b.im)
+      if (k == 0) {
+        Z[0] = make_float2(q.x, q.z);
+        Z[nh] = make_float2(q.y, q.w);
+      } else {
+        Z[k] = make_float2(q.x - q.w, q.y + q.z);
+        Z[nx - k] = make_float2(q.x + q.w, q.z - q.y);
+      }
     }
   }
   __syncthreads();
-  fft_lines<kEpt, true, true>(buf, tw, px, lines, 1, ls);
+  fft_lines<kEpt, true>(buf, tw, px, xd.lines, 1, ls);
 
   const float* bf = reinterpret_cast<const float*>(buf);
-  const int nvox = yb * nx;
-  for (int idx = threadIdx.x; idx < nvox; idx += blockDim.x) {
-    const int yy = idx / nx, x = idx - yy * nx;
-    const int i = (z * g.ny + y0 + yy) * nx + x;
-    float yv[3];
+  const int nitems = yb * q4;  // float4 runs of 4 voxels along x
+  constexpr int MI = 2;        // runs per thread (host checks yb * nx / 4 <= 2 * threads)
+  float4 yv[MI][3];
+  int gi[MI];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) yv[c] = bf[2 * ((c * (yb / 2) + (yy >> 1)) * ls + x) + (yy & 1)];
+  for (int it = 0; it < MI; ++it) {
+    const int idx = threadIdx.x + it * nthr;
+    if (idx < nitems) {
+      const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
+      gi[it] = (z * g.ny + y0 + yy) * nx + 4 * x4;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float* rowp = bf + 2 * ((c * yb2 + (yy >> 1)) * ls + 4 * x4) + (yy & 1);
+        yv[it][c] = make_float4(rowp[0], rowp[2], rowp[4], rowp[6]);
+      }
+    }
+  }
 
-    if (MODE == kOutY) {
+  if (MODE == kOutY) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.out[c * g.V + i] = yv[c];
-    } else if (MODE == kIter) {
-      float t[3], av[3], j[3], v[3];
+    for (int it = 0; it < MI; ++it)
+      if (threadIdx.x + it * nthr < nitems)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float s = a.s1[c * g.V + i];
-        if (a.s2) s = fmaf(a.gamma, s - a.s2[c * g.V + i], s);
-        t[c] = s;
-        av[c] = 2.0f * yv[c] - s;
-        j[c] = a.J[c * g.V + i];
+        for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
+  } else if (MODE == kIter) {
+    // all global loads of every run first (out may alias s2)
+    float4 s1v[MI][3], s2v[MI][3], jv[MI][3], rv[MI];
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      if (threadIdx.x + it * nthr < nitems) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          s1v[it][c] = ld4(a.s1 + c * g.V + gi[it]);
+          if (a.s2) s2v[it][c] = ld4(a.s2 + c * g.V + gi[it]);
+          jv[it][c] = ld4(a.J + c * g.V + gi[it]);
+        }
+        rv[it] = ld4(a.r + gi[it]);
       }
-      data_step(av, j, a.r[i], a.theta, a.eps, a.data_term, v);
+    }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        // s^k = v + b_hat = v + t - y
-        a.out[c * g.V + i] = v[c] + (t[c] - yv[c]);
-        if (a.v_out) a.v_out[c * g.V + i] = v[c];
-      }
-    } else if (MODE == kFinalWB) {
+    for (int it = 0; it < MI; ++it) {
+      if (threadIdx.x + it * nthr < nitems) {
+        float4 so[3], vo[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        a.out[c * g.V + i] = yv[c];
-        if (a.b_out) a.b_out[c * g.V + i] = a.s1[c * g.V + i] - yv[c];
-      }
-    } else {  // kCompose: u_new = w + u_old(x + w), optional warped image
-      const int x0 = x, yg = y0 + yy;
-      const Tap t = make_tap(x0, yg, z, yv[0], yv[1], yv[2], g);
-      float un[3];
+        for (int e = 0; e < 4; ++e) {
+          float t[3], av[3], j[3], v[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        un[c] = yv[c] + sample(a.u_old + c * g.V, t);
-        a.out[c * g.V + i] = un[c];
-        if (a.vel_out) a.vel_out[c * g.V + i] = yv[c];
+          for (int c = 0; c < 3; ++c) {
+            float s = f4get(s1v[it][c], e);
+            if (a.s2) s = fmaf(a.gamma, s - f4get(s2v[it][c], e), s);
+            t[c] = s;
+            av[c] = 2.0f * f4get(yv[it][c], e) - s;
+            j[c] = f4get(jv[it][c], e);
+          }
+          data_step(av, j, f4get(rv[it], e), a.theta, a.eps, a.data_term, v);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            // s^k = v + b_hat = v + t - y
+            f4set(so[c], e, v[c] + (t[c] - f4get(yv[it][c], e)));
+            f4set(vo[c], e, v[c]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          st4(a.out + c * g.V + gi[it], so[c]);
+          if (a.v_out) st4(a.v_out + c * g.V + gi[it], vo[c]);
+        }
       }
-      if (a.iw_out) {
-        const Tap t2 = make_tap(x0, yg, z, un[0], un[1], un[2], g);
-        a.iw_out[i] = sample(a.img, t2);
+    }
+  } else if (MODE == kFinalWB) {
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      if (threadIdx.x + it * nthr < nitems) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float4 y4 = yv[it][c];
+          if (a.b_out) {
+            const float4 s4 = ld4(a.s1 + c * g.V + gi[it]);
+            st4(a.b_out + c * g.V + gi[it],
+                make_float4(s4.x - y4.x, s4.y - y4.y, s4.z - y4.z, s4.w - y4.w));
+          }
+          st4(a.out + c * g.V + gi[it], y4);
+        }
+      }
+    }
+  } else {  // kCompose: u_new = w + u_old(x + w), optional warped image
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      const int idx = threadIdx.x + it * nthr;
+      if (idx < nitems) {
+        const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
+        float4 un[3], iw;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float w0 = f4get(yv[it][0], e), w1 = f4get(yv[it][1], e), w2 = f4get(yv[it][2], e);
+          const Tap t = make_tap(4 * x4 + e, y0 + yy, z, w0, w1, w2, g);
+          const float u0 = w0 + sample(a.u_old, t);
+          const float u1 = w1 + sample(a.u_old + g.V, t);
+          const float u2 = w2 + sample(a.u_old + 2 * g.V, t);
+          f4set(un[0], e, u0);
+          f4set(un[1], e, u1);
+          f4set(un[2], e, u2);
+          if (a.iw_out) {
+            const Tap t2 = make_tap(4 * x4 + e, y0 + yy, z, u0, u1, u2, g);
+            f4set(iw, e, sample(a.img, t2));
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          st4(a.out + c * g.V + gi[it], un[c]);
+          if (a.vel_out) st4(a.vel_out + c * g.V + gi[it], yv[it][c]);
+        }
+        if (a.iw_out) st4(a.iw_out + gi[it], iw);
       }
     }
   }
@@ -542,11 +734,12 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, PassCMode mode, const 
   const int yb = xline_rows(g.ny);
   const dim3 grid(g.ny / yb, g.nz), block(xline_threads(g));
   const size_t lds = pass_a_lds(g);
+  const XDivs xd = make_xdivs(g);
   switch (mode) {
-    case kOutY: hipLaunchKernelGGL(k_pass_c<kOutY>, grid, block, lds, st, g, px, yb, a); break;
-    case kIter: hipLaunchKernelGGL(k_pass_c<kIter>, grid, block, lds, st, g, px, yb, a); break;
-    case kFinalWB: hipLaunchKernelGGL(k_pass_c<kFinalWB>, grid, block, lds, st, g, px, yb, a); break;
-    default: hipLaunchKernelGGL(k_pass_c<kCompose>, grid, block, lds, st, g, px, yb, a); break;
+    case kOutY: hipLaunchKernelGGL(k_pass_c<kOutY>, grid, block, lds, st, g, px, xd, a); break;
+    case kIter: hipLaunchKernelGGL(k_pass_c<kIter>, grid, block, lds, st, g, px, xd, a); break;
+    case kFinalWB: hipLaunchKernelGGL(k_pass_c<kFinalWB>, grid, block, lds, st, g, px, xd, a); break;
+    default: hipLaunchKernelGGL(k_pass_c<kCompose>, grid, block, lds, st, g, px, xd, a); break;
   }
   return hipGetLastError();
 }

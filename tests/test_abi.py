@@ -1,0 +1,130 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2109_12688_amd import _lib
+from paper_2109_12688_amd._lib import Dims, Params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nadmm.h")
+
+FAKE = ctypes.c_void_p(0x10000)       # aligned stand-in pointer: never dereferenced on error paths
+MISALIGNED = ctypes.c_void_p(0x10004)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2109_12688_amd.build import build
+        build()
+    return _lib.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nadmm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_functions_are_exported(lib):
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_abi_version_and_status_strings(lib):
+    assert lib.nadmm_abi_version() == 1
+    for code, name in _lib.STATUS_NAMES.items():
+        assert lib.nadmm_status_string(code).decode() == name
+
+
+def _p(**kw):
+    base = dict(lambda_=0.01, theta=0.1, order=2, data_term=2, eps=1e-8, outer=2, iters=3)
+    base.update(kw)
+    return Params(**base)
+
+
+def ws_size(lib, d):
+    n = ctypes.c_size_t(0)
+    st = lib.nadmm_workspace_size(d, None, ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size(lib):
+    st, n = ws_size(lib, Dims(128, 128, 96))
+    assert st == 0
+    V = 128 * 128 * 96
+    assert 17 * 4 * V <= n <= 17 * 4 * V + 64 * 1024
+    assert lib.nadmm_workspace_size(Dims(128, 128, 96), None, None) == 1
+
+
+@pytest.mark.parametrize("d", [(128, 128, 7), (6, 4, 4), (128, 129, 96), (512, 16, 16),
+                               (32, 256, 96), (0, 8, 8), (-8, 8, 8), (4, 4, 2)])
+def test_unsupported_sizes(lib, d):
+    st, _ = ws_size(lib, Dims(*d))
+    assert st == 2, lib.nadmm_last_error()
+    p = _p()
+    st = lib.nadmm_register(Dims(*d), ctypes.byref(p), FAKE, FAKE, None, FAKE, None, None, FAKE,
+                            1 << 40, None)
+    assert st == 2
+    assert b"dims" in lib.nadmm_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(theta=0.0), dict(theta=-1.0), dict(theta=float("nan")),
+                                dict(lambda_=-0.1), dict(lambda_=float("inf")), dict(order=0),
+                                dict(order=5), dict(data_term=3), dict(data_term=1, eps=0.0),
+                                dict(iters=0), dict(outer=-1)])
+def test_bad_params(lib, kw):
+    p = _p(**kw)
+    d = Dims(32, 32, 32)
+    st = lib.nadmm_register(d, ctypes.byref(p), FAKE, FAKE, None, FAKE, None, None, FAKE, 1 << 40, None)
+    assert st == 1, lib.nadmm_last_error()
+
+
+def test_null_and_misaligned_pointers(lib):
+    p = _p()
+    d = Dims(32, 32, 32)
+    big = ctypes.c_size_t(1 << 40)
+    assert lib.nadmm_register(d, None, FAKE, FAKE, None, FAKE, None, None, FAKE, big, None) == 1
+    assert lib.nadmm_register(d, ctypes.byref(p), None, FAKE, None, FAKE, None, None, FAKE, big, None) == 1
+    assert lib.nadmm_register(d, ctypes.byref(p), FAKE, MISALIGNED, None, FAKE, None, None, FAKE, big, None) == 1
+    assert b"aligned" in lib.nadmm_last_error()
+    assert lib.nadmm_admm(d, ctypes.byref(p), FAKE, FAKE, None, None, None, FAKE, big, None) == 1
+    assert lib.nadmm_warp(d, FAKE, FAKE, None, FAKE, None, FAKE, None) == 1  # resid needs ref
+    assert lib.nadmm_compose(d, FAKE, ctypes.c_void_p(0x20000), FAKE, None) == 1  # out aliases u
+    assert lib.nadmm_expmap(d, FAKE, 31, ctypes.c_void_p(0x20000), FAKE, big, None) == 1
+    assert lib.nadmm_expmap(d, FAKE, 3, FAKE, FAKE, big, None) == 1  # out aliases vel
+
+
+def test_workspace_too_small(lib):
+    p = _p()
+    d = Dims(32, 32, 32)
+    _, need = ws_size(lib, d)
+    st = lib.nadmm_register(d, ctypes.byref(p), FAKE, FAKE, None, FAKE, None, None, FAKE,
+                            ctypes.c_size_t(need - 1), None)
+    assert st == 3
+    assert lib.nadmm_admm(d, ctypes.byref(p), FAKE, FAKE, FAKE, None, None, None, need, None) == 1
+    st = lib.nadmm_jacobian(d, FAKE, None, FAKE, FAKE, FAKE, ctypes.c_size_t(16), None)
+    assert st == 3
+    st = lib.nadmm_fourier_solve(d, ctypes.byref(p), FAKE, FAKE, FAKE, ctypes.c_size_t(need // 2), None)
+    assert st == 3
+
+
+def test_profile_read_without_records(lib):
+    assert lib.nadmm_profile_enable(0) == 0
+    prof = _lib.profile_read()
+    assert prof == {}
+
+
+def test_python_binding_rejects_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    from paper_2109_12688_amd import api
+    x = torch.zeros(4, 4, 8)
+    with pytest.raises(ValueError):
+        api.warp(x, torch.zeros(3, 4, 4, 8))
