@@ -131,10 +131,10 @@ nadmm_status check_ptr(const void* p, const char* name, bool nullable) {
     if (s_ != NADMM_OK) return s_;          \
   } while (0)
 
-// Workspace: 17 float32 fields of V values (each region 256-byte aligned)
-// plus the Jacobian partials.
+// Workspace: 17 float32 fields of V values (each region 256-byte aligned),
+// the Jacobian partials and the transform tables (a few KB).
 struct Layout {
-  size_t J, r, iw, s1, s2, X, u, jac, total;
+  size_t J, r, iw, s1, s2, X, u, jac, tab, total;
 };
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -149,9 +149,10 @@ Layout layout(const nadmm_dims& d) {
   L.iw = o; o += f1;
   L.s1 = o; o += f3;
   L.s2 = o; o += f3;
-  L.X = o; o += f3;
+  L.X = o; o += align256((size_t)3 * (d.nx / 2 + 1) * d.ny * d.nz * 2 * sizeof(float));
   L.u = o; o += f3;
   L.jac = o; o += align256(kJacBlocks * 4 * sizeof(double));
+  L.tab = o; o += align256(tables_bytes(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}));
   L.total = o;
   return L;
 }
@@ -192,25 +193,26 @@ Plans plans(const nadmm_dims& d) { return Plans{make_plan(d.nx), make_plan(d.ny)
 
 // One application of the w-step operator S to t = s1 + gamma (s1 - s2)
 // through passes A and B; pass C (with its mode) is issued by the caller.
-hipError_t spectral_ab(const Geo& g, const Plans& pl, const nadmm_params* p, const float* s1,
-                       const float* s2, float gamma, float2* X, hipStream_t st) {
-  hipError_t e = timed(KK_PASS_A, st, [&] { return launch_pass_a(g, pl.x, s1, s2, gamma, X, st); });
+hipError_t spectral_ab(const Geo& g, const Plans& pl, const Tables& tb, const nadmm_params* p,
+                       const float* s1, const float* s2, float gamma, float2* X, hipStream_t st) {
+  hipError_t e =
+      timed(KK_PASS_A, st, [&] { return launch_pass_a(g, pl.x, tb, s1, s2, gamma, X, st); });
   if (e != hipSuccess) return e;
   return timed(KK_PASS_B, st, [&] {
-    return launch_pass_b(g, pl.y, pl.z, X, (float)p->lambda, (float)p->theta, p->order, st);
+    return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
   });
 }
 
 // The ADMM loop of one warping, in the two-field form: s^0 already in S1.
 // Runs iterations k = 1 .. iters-1 and leaves s^{iters-1} in *cur.
-nadmm_status admm_iterations(const Geo& g, const Plans& pl, const nadmm_params* p,
-                             const float* J, const float* r, float*& cur, float*& prev,
-                             float2* X, float* v_last, hipStream_t st) {
+nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
+                             const nadmm_params* p, const float* J, const float* r, float*& cur,
+                             float*& prev, float2* X, float* v_last, hipStream_t st) {
   const std::vector<double> gam = nesterov_gammas(p->iters);
   for (int k = 1; k < p->iters; ++k) {
     const float gk = (float)gam[k - 1];
     const float* s2 = (k == 1) ? nullptr : prev;  // gamma_0 = 0: s^{-1} never read
-    HIP_TRY(spectral_ab(g, pl, p, cur, s2, gk, X, st));
+    HIP_TRY(spectral_ab(g, pl, tb, p, cur, s2, gk, X, st));
     PassCArgs a{};
     a.X = X;
     a.s1 = cur;
@@ -223,7 +225,7 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const nadmm_params* 
     a.data_term = p->data_term;
     a.out = prev;  // s^k overwrites s^{k-2} voxel by voxel
     a.v_out = (k == p->iters - 1) ? v_last : nullptr;
-    HIP_TRY(timed(KK_PASS_C_ITER, st, [&] { return launch_pass_c(g, pl.x, kIter, a, st); }));
+    HIP_TRY(timed(KK_PASS_C_ITER, st, [&] { return launch_pass_c(g, pl.x, tb, kIter, a, st); }));
     float* tmp = cur;
     cur = prev;
     prev = tmp;
@@ -283,6 +285,8 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p, const float* fi
   float* S2 = at<float>(workspace, L.s2);
   float2* X = at<float2>(workspace, L.X);
   float* U = at<float>(workspace, L.u);
+  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
+  HIP_TRY(launch_tables(g, tb, st));
 
   // Displacement buffers alternate between U and disp so that the last
   // warping writes disp.
@@ -309,9 +313,9 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p, const float* fi
                               p->data_term, st); }));
     float* cur = S1;
     float* prev = S2;
-    CHECK(admm_iterations(g, pl, p, J, r, cur, prev, X, nullptr, st));
+    CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, nullptr, st));
     // final w = S s^{K-1}, composed onto the displacement
-    HIP_TRY(spectral_ab(g, pl, p, cur, nullptr, 0.0f, X, st));
+    HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st));
     PassCArgs a{};
     a.X = X;
     a.out = dst_of(c);
@@ -319,7 +323,7 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p, const float* fi
     a.img = moving;
     a.iw_out = last ? warped : iw;
     a.vel_out = velocities ? velocities + (size_t)c * 3 * V : nullptr;
-    HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_pass_c(g, pl.x, kCompose, a, st); }));
+    HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_pass_c(g, pl.x, tb, kCompose, a, st); }));
     u_src = a.out;
   }
   return NADMM_OK;
@@ -343,18 +347,20 @@ nadmm_status nadmm_admm(nadmm_dims d, const nadmm_params* p, const float* J, con
   float* S1 = at<float>(workspace, L.s1);
   float* S2 = at<float>(workspace, L.s2);
   float2* X = at<float2>(workspace, L.X);
+  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
+  HIP_TRY(launch_tables(g, tb, st));
   HIP_TRY(timed(KK_ADMM_INIT, st, [&] { return launch_admm_init(g, J, r, S1, p->iters == 1 ? v_out : nullptr, (float)p->theta,
                            (float)p->eps, p->data_term, st); }));
   float* cur = S1;
   float* prev = S2;
-  CHECK(admm_iterations(g, pl, p, J, r, cur, prev, X, v_out, st));
-  HIP_TRY(spectral_ab(g, pl, p, cur, nullptr, 0.0f, X, st));
+  CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, v_out, st));
+  HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st));
   PassCArgs a{};
   a.X = X;
   a.s1 = cur;
   a.out = w_out;
   a.b_out = b_out;
-  HIP_TRY(timed(KK_PASS_C_WB, st, [&] { return launch_pass_c(g, pl.x, kFinalWB, a, st); }));
+  HIP_TRY(timed(KK_PASS_C_WB, st, [&] { return launch_pass_c(g, pl.x, tb, kFinalWB, a, st); }));
   return NADMM_OK;
 }
 
@@ -370,11 +376,13 @@ nadmm_status nadmm_fourier_solve(nadmm_dims d, const nadmm_params* p, const floa
   const Layout L = layout(d);
   hipStream_t st = static_cast<hipStream_t>(stream);
   float2* X = at<float2>(workspace, L.X);
-  HIP_TRY(spectral_ab(g, pl, p, s, nullptr, 0.0f, X, st));
+  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
+  HIP_TRY(launch_tables(g, tb, st));
+  HIP_TRY(spectral_ab(g, pl, tb, p, s, nullptr, 0.0f, X, st));
   PassCArgs a{};
   a.X = X;
   a.out = w;
-  HIP_TRY(timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c(g, pl.x, kOutY, a, st); }));
+  HIP_TRY(timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c(g, pl.x, tb, kOutY, a, st); }));
   return NADMM_OK;
 }
 
@@ -469,6 +477,7 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   float* S2 = at<float>(workspace, L.s2);
   float2* X = at<float2>(workspace, L.X);
   const float gamma = (float)nesterov_gammas(3)[2];
+  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
   PassCArgs a{};
   a.X = X;
   a.s1 = S1;
@@ -481,10 +490,9 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   a.data_term = p->data_term;
   a.out = S2;
   auto launch = [&]() -> hipError_t {
-    if (kind == 0) return launch_pass_a(g, pl.x, S1, S2, gamma, X, st);
-    if (kind == 1)
-      return launch_pass_b(g, pl.y, pl.z, X, (float)p->lambda, (float)p->theta, p->order, st);
-    return launch_pass_c(g, pl.x, kIter, a, st);
+    if (kind == 0) return launch_pass_a(g, pl.x, tb, S1, S2, gamma, X, st);
+    if (kind == 1) return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
+    return launch_pass_c(g, pl.x, tb, kIter, a, st);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));

@@ -23,17 +23,13 @@ namespace nadmm {
 
 // q = floor(n / d) = (n * m) >> 32 with m = ceil(2^32 / d); exact for n, d < 2^16.
 struct FastDiv {
-  uint32_t d;
-  uint32_t pad;
-  uint64_t m;
+  uint32_t d = 1;
+  uint32_t pad = 0;
+  uint64_t m = 0;
 };
 
-inline FastDiv make_fastdiv(uint32_t d) {
-  FastDiv f;
-  f.d = d;
-  f.pad = 0;
-  f.m = ((uint64_t(1) << 32) + d - 1) / d;
-  return f;
+constexpr FastDiv make_fastdiv(uint32_t d) {
+  return FastDiv{d, 0u, ((uint64_t(1) << 32) + d - 1) / d};
 }
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
@@ -41,8 +37,8 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
 }
 
 struct FftStage {
-  int R, Ns, nb, twstride;  // radix, span of earlier stages, N / R, N / (Ns R)
-  FastDiv div_nb, div_ns;
+  int R = 0, Ns = 0, nb = 0, twstride = 0;  // radix, span of earlier stages, N / R, N / (Ns R)
+  FastDiv div_nb{}, div_ns{};
 };
 
 struct FftPlan {
@@ -196,11 +192,20 @@ struct Dft<12, INV> : DftComposite<4, 3, INV> {};
 template <bool INV>
 struct Dft<16, INV> : DftComposite<4, 4, INV> {};
 
+// Position of element e inside a line: with PADSH > 0 one slot of padding
+// follows every 2^PADSH elements (breaks the stride-R writes of early
+// Stockham stages across LDS banks).
+template <int PADSH>
+__device__ __forceinline__ int lpad(int e) {
+  return PADSH > 0 ? e + (e >> PADSH) : e;
+}
+
 // One Stockham radix-R stage over `nlines` lines.  Element e of line l lives
-// at buf[l * ls + e * es].  Consecutive threads take consecutive lines
-// (lines are laid out so that this is bank-conflict free).  The caller
-// guarantees nlines * N / R <= MAXB * blockDim.x.
-template <int R, int MAXB, bool INV>
+// at buf[l * ls + lpad<PADSH>(e) * es].  LINE_FAST maps consecutive threads
+// to consecutive lines (for lines adjacent in LDS), otherwise to consecutive
+// butterflies of one line.  The caller guarantees
+// nlines * N / R <= MAXB * blockDim.x.
+template <int R, int MAXB, bool INV, bool LINE_FAST, int PADSH>
 __device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, const FftStage& s,
                                           const FastDiv& dl, int es, int ls) {
   const int nlines = (int)dl.d;
@@ -212,32 +217,44 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, const F
   for (int i = 0; i < MAXB; ++i) {
     const int b = threadIdx.x + i * nthr;
     if (b < total) {
-      const int j = (int)fdiv((uint32_t)b, dl);
-      const int line = b - j * nlines;
+      int j, line;
+      if (LINE_FAST) {
+        j = (int)fdiv((uint32_t)b, dl);
+        line = b - j * nlines;
+      } else {
+        line = (int)fdiv((uint32_t)b, s.div_nb);
+        j = b - line * s.nb;
+      }
       const int k = j - (int)fdiv((uint32_t)j, s.div_ns) * s.Ns;
-      kk[i] = k;
-      base[i] = line * ls + ((j - k) * R + k) * es;
-      const float2* src = buf + line * ls + j * es;
+      base[i] = line * ls;
+      // low 16 bits: k = j mod Ns; high bits: destination element of r = 0
+      kk[i] = k | (((j - k) * R + k) << 16);
+      const float2* src = buf + line * ls;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src[r * s.nb * es];
+      for (int r = 0; r < R; ++r) v[i][r] = src[lpad<PADSH>(j + r * s.nb) * es];
     }
   }
   __syncthreads();
+  const int twstride = s.twstride;
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     const int b = threadIdx.x + i * nthr;
     if (b < total) {
-      const int step = kk[i] * s.twstride;
+      const int k = kk[i] & 0xffff;
+      const int d0 = kk[i] >> 16;
+      if (s.Ns > 1) {  // the first stage's twiddles are all 1
+        const int step = k * twstride;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * step];
-        if (INV) w.y = -w.y;
-        v[i][r] = cmul(v[i][r], w);
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * step];
+          if (INV) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
       }
       Dft<R, INV>::run(v[i]);
       float2* dst = buf + base[i];
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * s.Ns * es] = v[i][r];
+      for (int r = 0; r < R; ++r) dst[lpad<PADSH>(d0 + r * s.Ns) * es] = v[i][r];
     }
   }
   __syncthreads();
@@ -245,20 +262,276 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, const F
 
 // Full transform of every line; EPT bounds the elements per thread of any
 // stage (nlines * N <= EPT * blockDim.x), which the host checks.
-template <int EPT, bool INV>
+template <int EPT, bool INV, bool LINE_FAST = true, int PADSH = 0>
 __device__ void fft_lines(float2* buf, const float2* tw, const FftPlan& plan, const FastDiv& dl,
                           int es, int ls) {
   for (int s = 0; s < plan.nstages; ++s) {
     const FftStage& st = plan.st[s];
     switch (st.R) {
-      case 16: fft_stage<16, (EPT + 15) / 16, INV>(buf, tw, st, dl, es, ls); break;
-      case 12: fft_stage<12, (EPT + 11) / 12, INV>(buf, tw, st, dl, es, ls); break;
-      case 8: fft_stage<8, (EPT + 7) / 8, INV>(buf, tw, st, dl, es, ls); break;
-      case 6: fft_stage<6, (EPT + 5) / 6, INV>(buf, tw, st, dl, es, ls); break;
-      case 4: fft_stage<4, (EPT + 3) / 4, INV>(buf, tw, st, dl, es, ls); break;
-      case 3: fft_stage<3, (EPT + 2) / 3, INV>(buf, tw, st, dl, es, ls); break;
-      default: fft_stage<2, (EPT + 1) / 2, INV>(buf, tw, st, dl, es, ls); break;
+      case 16: fft_stage<16, (EPT + 15) / 16, INV, LINE_FAST, PADSH>(buf, tw, st, dl, es, ls); break;
+      case 12: fft_stage<12, (EPT + 11) / 12, INV, LINE_FAST, PADSH>(buf, tw, st, dl, es, ls); break;
+      case 8: fft_stage<8, (EPT + 7) / 8, INV, LINE_FAST, PADSH>(buf, tw, st, dl, es, ls); break;
+      case 6: fft_stage<6, (EPT + 5) / 6, INV, LINE_FAST, PADSH>(buf, tw, st, dl, es, ls); break;
+      case 4: fft_stage<4, (EPT + 3) / 4, INV, LINE_FAST, PADSH>(buf, tw, st, dl, es, ls); break;
+      case 3: fft_stage<3, (EPT + 2) / 3, INV, LINE_FAST, PADSH>(buf, tw, st, dl, es, ls); break;
+      default: fft_stage<2, (EPT + 1) / 2, INV, LINE_FAST, PADSH>(buf, tw, st, dl, es, ls); break;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-team FFTs: every line is transformed by a team of L lanes of ONE
+// wavefront, so the stages of a line need no workgroup barrier; LDS
+// operations of a wavefront are performed in issue order and the fences
+// below only stop the compiler from moving them.  Inside a wavefront, lane
+// = tl * (64 / L) + li: li picks one of the 64 / L lines the wavefront owns
+// (consecutive lanes touch consecutive lines, which the LDS layouts keep on
+// distinct banks), tl the team lane, which takes butterflies tl, tl + L, ...
+// of every stage.  The host planner only picks radices with L | N / R.
+// ---------------------------------------------------------------------------
+struct TeamPlan {
+  int n = 0, nstages = -1, L = 1;
+  FftStage st[4] = {};
+};
+
+// Planner (usable on the host and at compile time).  Points per lane are
+// bounded by kTeamEpt; the team size L <= max_lanes is a power of two and
+// every stage's butterfly count n / R must be a multiple of L; plans with
+// the fewest stages win, larger L on ties.
+constexpr int kTeamEpt = 27;
+
+constexpr void team_fill(TeamPlan& p, const int* rad) {
+  int ns = 1;
+  for (int i = 0; i < p.nstages; ++i) {
+    FftStage& s = p.st[i];
+    s.R = rad[i];
+    s.Ns = ns;
+    s.nb = p.n / s.R;
+    s.twstride = p.n / (ns * s.R);
+    s.div_nb = make_fastdiv(s.nb);
+    s.div_ns = make_fastdiv(ns);
+    ns *= s.R;
+  }
+}
+
+constexpr bool team_search(int n, int m, int L, int depth, int* out) {
+  const int radices[7] = {16, 12, 8, 6, 4, 3, 2};
+  if (m == 1) return depth == 0;
+  if (depth == 0) return false;
+  for (int i = 0; i < 7; ++i) {
+    const int R = radices[i];
+    if (m % R == 0 && (n / R) % L == 0 && team_search(n, m / R, L, depth - 1, out + 1)) {
+      out[0] = R;
+      return true;
+    }
+  }
+  return false;
+}
+
+constexpr TeamPlan make_team_plan_ce(int n, int max_lanes) {
+  TeamPlan best{};
+  best.n = n;
+  best.nstages = -1;
+  const int Ls[5] = {16, 8, 4, 2, 1};
+  for (int li = 0; li < 5; ++li) {
+    const int L = Ls[li];
+    if (L > max_lanes || n % L || n / L > kTeamEpt) continue;
+    int rad[4] = {0, 0, 0, 0};
+    for (int depth = 1; depth <= 4; ++depth) {
+      if (team_search(n, n, L, depth, rad)) {
+        if (best.nstages < 0 || depth < best.nstages) {
+          best.nstages = depth;
+          best.L = L;
+          team_fill(best, rad);
+        }
+        break;
+      }
+    }
+  }
+  return best;
+}
+
+constexpr TeamPlan reverse_team_plan_ce(const TeamPlan& p) {
+  TeamPlan q = p;
+  int rad[4] = {0, 0, 0, 0};
+  for (int i = 0; i < p.nstages; ++i) rad[i] = p.st[p.nstages - 1 - i].R;
+  team_fill(q, rad);
+  return q;
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Butterfly j of a stage: load its R inputs of a line.
+template <int R, int PADSH>
+__device__ __forceinline__ void team_load(const float2* line, int es, const FftStage& s, int j,
+                                          float2* v) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = line[lpad<PADSH>(j + r * s.nb) * es];
+}
+
+// Twiddle and DFT of butterfly j in registers.
+template <int R, bool INV>
+__device__ __forceinline__ void team_compute(const float2* tw, const FftStage& s, int j,
+                                             float2* v) {
+  if (s.Ns > 1) {
+    const int k = j - (int)fdiv((uint32_t)j, s.div_ns) * s.Ns;
+    const int step = k * s.twstride;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      float2 w = tw[r * step];
+      if (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+  }
+  Dft<R, INV>::run(v);
+}
+
+template <int R, int PADSH>
+__device__ __forceinline__ void team_store(float2* line, int es, const FftStage& s, int j,
+                                           const float2* v) {
+  const int k = j - (int)fdiv((uint32_t)j, s.div_ns) * s.Ns;
+  const int d0 = (j - k) * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) line[lpad<PADSH>(d0 + r * s.Ns) * es] = v[r];
+}
+
+// One stage of a team over its line: all loads, then (fenced) all stores.
+// Source and destination may differ (e.g. a row in global memory and its
+// padded copy in LDS); element e lives at src[lpad<PADS>(e) * ses] and
+// dst[lpad<PADD>(e) * des].
+template <int R, int EPT, bool INV, int PADS, int PADD>
+__device__ __forceinline__ void team_stage_io(const float2* src, int ses, float2* dst, int des,
+                                              const float2* tw, const FftStage& s, int L, int tl) {
+  constexpr int M = EPT / R;  // nm * R = n / L <= EPT, so nm <= EPT / R
+  const int nm = s.nb / L;     // butterflies per lane (exact by the plan)
+  float2 v[M][R];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    if (m < nm) team_load<R, PADS>(src, ses, s, tl + m * L, v[m]);
+  wave_lds_fence();
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    if (m < nm) {
+      team_compute<R, INV>(tw, s, tl + m * L, v[m]);
+      team_store<R, PADD>(dst, des, s, tl + m * L, v[m]);
+    }
+  wave_lds_fence();
+}
+
+template <int R, int EPT, bool INV, int PADSH>
+__device__ __forceinline__ void team_stage(float2* line, const float2* tw, const FftStage& s,
+                                           int L, int tl, int es) {
+  team_stage_io<R, EPT, INV, PADSH, PADSH>(line, es, line, es, tw, s, L, tl);
+}
+
+template <int EPT, bool INV, int PADS, int PADD>
+__device__ __forceinline__ void team_stage_io_any(const float2* src, int ses, float2* dst, int des,
+                                                  const float2* tw, const FftStage& s, int L,
+                                                  int tl) {
+  switch (s.R) {
+    case 16: team_stage_io<16, EPT, INV, PADS, PADD>(src, ses, dst, des, tw, s, L, tl); break;
+    case 12: team_stage_io<12, EPT, INV, PADS, PADD>(src, ses, dst, des, tw, s, L, tl); break;
+    case 8: team_stage_io<8, EPT, INV, PADS, PADD>(src, ses, dst, des, tw, s, L, tl); break;
+    case 6: team_stage_io<6, EPT, INV, PADS, PADD>(src, ses, dst, des, tw, s, L, tl); break;
+    case 4: team_stage_io<4, EPT, INV, PADS, PADD>(src, ses, dst, des, tw, s, L, tl); break;
+    case 3: team_stage_io<3, EPT, INV, PADS, PADD>(src, ses, dst, des, tw, s, L, tl); break;
+    default: team_stage_io<2, EPT, INV, PADS, PADD>(src, ses, dst, des, tw, s, L, tl); break;
+  }
+}
+
+template <int EPT, bool INV, int PADSH>
+__device__ __forceinline__ void team_stage_any(float2* line, const float2* tw, const FftStage& s,
+                                               int L, int tl, int es) {
+  switch (s.R) {
+    case 16: team_stage<16, EPT, INV, PADSH>(line, tw, s, L, tl, es); break;
+    case 12: team_stage<12, EPT, INV, PADSH>(line, tw, s, L, tl, es); break;
+    case 8: team_stage<8, EPT, INV, PADSH>(line, tw, s, L, tl, es); break;
+    case 6: team_stage<6, EPT, INV, PADSH>(line, tw, s, L, tl, es); break;
+    case 4: team_stage<4, EPT, INV, PADSH>(line, tw, s, L, tl, es); break;
+    case 3: team_stage<3, EPT, INV, PADSH>(line, tw, s, L, tl, es); break;
+    default: team_stage<2, EPT, INV, PADSH>(line, tw, s, L, tl, es); break;
+  }
+}
+
+// Stages [s0, s1) of the plan on every line.  The plan must live in LDS (or
+// other addressable memory): stages are indexed at run time.
+// LINEPAD: line l starts at lpad<PADSH>(l) * ls instead of l * ls (used when
+// the lines are the padded columns of a row-major plane).
+template <int EPT, bool INV, int PADSH = 0, bool LINEPAD = false>
+__device__ __forceinline__ void team_fft(float2* buf, const float2* tw, const TeamPlan& p,
+                                         int nlines, int es, int ls, int s0 = 0, int s1 = 4) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int nlw = 64 / p.L;
+  const int li = lane % nlw, tl = lane / nlw;
+  const int se = s1 < p.nstages ? s1 : p.nstages;
+  for (int l0 = wave * nlw; l0 < nlines; l0 += nwaves * nlw) {
+    const int l = l0 + li;
+    if (l < nlines) {
+      float2* line = buf + (LINEPAD ? lpad<PADSH>(l) : l) * ls;
+      for (int s = s0; s < se; ++s)
+        team_stage_any<EPT, INV, LINEPAD ? 0 : PADSH>(line, tw, p.st[s], p.L, tl, es);
+    }
+  }
+}
+
+// Last forward stage, a pointwise real multiplier on the spectrum, and the
+// first stage of the inverse plan (the forward radices reversed), fused in
+// registers: forward butterfly j of the last stage produces elements
+// j + r N/R, exactly the inputs of inverse butterfly j of the first stage.
+// The multiplier of spectral element e of this line is
+// theta / (theta + lambda (kq + ks[e])^order) * scale.
+struct SpectralMult {
+  const float* ks;
+  float kq, lambda, theta, scale;
+  int order;
+  __device__ __forceinline__ float operator()(int e) const {
+    const float k0 = kq + ks[e];
+    float kn = k0;
+    for (int i = 1; i < order; ++i) kn *= k0;
+    return theta * scale * __builtin_amdgcn_rcpf(theta + lambda * kn);
+  }
+};
+
+template <int R, int EPT, int PADSH>
+__device__ __forceinline__ void team_fused(float2* line, const float2* tw, const FftStage& sf,
+                                           const FftStage& si, int L, int tl, int es,
+                                           SpectralMult mult) {
+  constexpr int M = EPT / R;
+  const int nm = sf.nb / L;
+  float2 v[M * R];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    if (m < nm) team_load<R, PADSH>(line, es, sf, tl + m * L, v + m * R);
+  wave_lds_fence();
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    if (m < nm) {
+      const int j = tl + m * L;
+      float2* w = v + m * R;
+      team_compute<R, false>(tw, sf, j, w);
+#pragma unroll
+      for (int r = 0; r < R; ++r) w[r] = cscale(w[r], mult(j + r * sf.Ns));
+      Dft<R, true>::run(w);  // first inverse stage: all twiddles are 1
+      team_store<R, PADSH>(line, es, si, j, w);
+    }
+  wave_lds_fence();
+}
+
+template <int EPT, int PADSH>
+__device__ __forceinline__ void team_fused_any(float2* line, const float2* tw, const FftStage& sf,
+                                               const FftStage& si, int L, int tl, int es,
+                                               SpectralMult mult) {
+  switch (sf.R) {
+    case 16: team_fused<16, EPT, PADSH>(line, tw, sf, si, L, tl, es, mult); break;
+    case 12: team_fused<12, EPT, PADSH>(line, tw, sf, si, L, tl, es, mult); break;
+    case 8: team_fused<8, EPT, PADSH>(line, tw, sf, si, L, tl, es, mult); break;
+    case 6: team_fused<6, EPT, PADSH>(line, tw, sf, si, L, tl, es, mult); break;
+    case 4: team_fused<4, EPT, PADSH>(line, tw, sf, si, L, tl, es, mult); break;
+    case 3: team_fused<3, EPT, PADSH>(line, tw, sf, si, L, tl, es, mult); break;
+    default: team_fused<2, EPT, PADSH>(line, tw, sf, si, L, tl, es, mult); break;
   }
 }
 

@@ -20,8 +20,18 @@ int plane_threads(const Geo& g);
 // Elements-per-thread bound every LDS FFT stage is compiled for.
 constexpr int kEpt = 16;
 constexpr int kJacBlocks = 1024;
+constexpr int kMaxLds = 160 * 1024 - 1024;  // dynamic LDS budget of a workgroup (static use reserved)
 
 FftPlan make_plan(int n);
+// Points per lane bound of the wave-team FFTs, and their planner: the team
+// size L <= max_lanes (lanes per line, a power of two) and radices with
+// L | n / R for every stage, fewest stages first, larger L on ties.
+TeamPlan make_team_plan(int n, int max_lanes);
+TeamPlan reverse_team_plan(const TeamPlan& p);
+size_t plane_lds_bytes(const Geo& g, int rs);
+TeamPlan plane_plan_y(const Geo& g);
+TeamPlan plane_plan_z(const Geo& g);
+int plane_row_stride(const Geo& g);
 
 // Host-precomputed divisors of the x-line and y-z plane index maps.
 struct XDivs {
@@ -38,6 +48,21 @@ bool launch_shape_ok(const Geo& g);
 // Per-thread item bounds the batched loads are compiled for (checked on the host).
 constexpr int kXItems = 4;   // float4 groups per thread in the x-line passes
 constexpr int kPItems = 8;   // float4 (two complex) per thread in the plane pass
+
+// Transform tables, generated once per call into the workspace in float64
+// and rounded once: tw* = exp(-2 pi i k / n), s* = 2 - 2 cos(2 pi k / n)
+// = 4 sin^2(pi k / n) (the pieces of the Laplacian symbol; sx for k <= nx/2).
+struct Tables {
+  float2* twx;
+  float2* twy;
+  float2* twz;
+  float* sx;
+  float* sy;
+  float* sz;
+};
+size_t tables_bytes(const Geo& g);
+Tables tables_at(const Geo& g, void* base);
+hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 
 // Pass C (inverse x transform + pointwise update) output modes.
 enum PassCMode { kOutY = 0, kIter = 1, kFinalWB = 2, kCompose = 3 };
@@ -71,12 +96,12 @@ hipError_t launch_grad_resid(const Geo& g, const float* iw, const float* ref, fl
                              hipStream_t st);
 hipError_t launch_admm_init(const Geo& g, const float* J, const float* r, float* s0, float* v_out,
                             float theta, float eps, int data_term, hipStream_t st);
-hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const float* s1, const float* s2,
-                         float gamma, float2* X, hipStream_t st);
-hipError_t launch_pass_b(const Geo& g, const FftPlan& py, const FftPlan& pz, float2* X,
-                         float lambda, float theta, int order, hipStream_t st);
-hipError_t launch_pass_c(const Geo& g, const FftPlan& px, PassCMode mode, const PassCArgs& a,
-                         hipStream_t st);
+hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
+                         const float* s2, float gamma, float2* X, hipStream_t st);
+hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
+                         int order, hipStream_t st);
+hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
+                         const PassCArgs& a, hipStream_t st);
 hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out, hipStream_t st);
 hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* partial,
                            double* stats, int64_t* n_nonpos, hipStream_t st);

@@ -25,9 +25,29 @@
 //           next state (or the composition of the warping's velocity).
 #include <float.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
+// Layout of the x-line buffers of passes A and C: butterflies of one line on
+// consecutive threads (XL_LINE_FAST 0) and one padding slot every
+// 2^XL_PADSH complex elements, plus XL_EXTRA slots at the end of each line.
+#ifndef XL_LINE_FAST
+#define XL_LINE_FAST 0
+#endif
+#ifndef XL_PADSH
+#define XL_PADSH 4
+#endif
+static_assert(XL_PADSH == 0 || XL_PADSH >= 2, "float4 runs must not straddle a padding slot");
+#ifndef XL_EXTRA
+#define XL_EXTRA 0
+#endif
+
 namespace nadmm {
+
+static inline int xl_pad_host(int e) { return XL_PADSH > 0 ? e + (e >> XL_PADSH) : e; }
+// complex elements between consecutive x lines in LDS
+static inline int xline_stride(int nx) { return xl_pad_host(nx) + XL_EXTRA; }
 
 // ---------------------------------------------------------------------------
 // host-side geometry helpers
@@ -40,6 +60,12 @@ int xline_rows(int ny) {
 
 static int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
+// dynamic LDS of pass B for row stride rs: twiddles, symbol tables, plane
+size_t plane_lds_bytes(const Geo& g, int rs) {
+  return sizeof(float2) * (size_t)(g.ny + g.nz) + sizeof(float) * (size_t)(g.ny + g.nz + 1) +
+         sizeof(float2) * (size_t)g.nz * rs;
+}
+
 int xline_threads(const Geo& g) {
   const int elems = 3 * (xline_rows(g.ny) / 2) * g.nx;
   int t = round_up((elems + 7) / 8, 64);
@@ -48,9 +74,12 @@ int xline_threads(const Geo& g) {
   return t;
 }
 
+#ifndef PLANE_EPT_TARGET
+#define PLANE_EPT_TARGET 8
+#endif
 int plane_threads(const Geo& g) {
   const int elems = g.ny * g.nz;
-  int t = round_up((elems + 7) / 8, 64);
+  int t = round_up((elems + PLANE_EPT_TARGET - 1) / PLANE_EPT_TARGET, 64);
   if (t > 1024) t = 1024;
   if (t < 64) t = 64;
   return t;
@@ -96,6 +125,69 @@ FftPlan make_plan(int n) {
   return p;
 }
 
+TeamPlan make_team_plan(int n, int max_lanes) { return make_team_plan_ce(n, max_lanes); }
+TeamPlan reverse_team_plan(const TeamPlan& p) { return reverse_team_plan_ce(p); }
+
+// Row stride (complex) of the padded [z][y] plane of pass B: element (z, y)
+// lives at z * rs + y + y / 16.  rs is chosen by simulating the first-stage
+// LDS reads of both phases (y rows and z columns) of one wavefront, counting
+// lanes of each group of 16 that share a bank pair (32 banks of 4 bytes,
+// 16 lanes per cycle for 8-byte accesses), subject to fitting in LDS.
+static int ypad(int y) { return y + (y >> 4); }
+static int plane_conflicts(const TeamPlan& p, int nlines, int rs, bool rows) {
+  const int nlw = 64 / p.L;
+  int score = 0;
+  for (int grp = 0; grp < 4; ++grp) {
+    int count[16] = {0};
+    for (int lane = 16 * grp; lane < 16 * grp + 16; ++lane) {
+      const int li = lane % nlw, tl = lane / nlw;
+      if (li >= nlines) continue;
+      const int j = tl;  // first butterfly, element r = 0
+      const int a = rows ? li * rs + ypad(j) : j * rs + ypad(li);
+      ++count[a & 15];
+    }
+    int mx = 0;
+    for (int b = 0; b < 16; ++b) mx = count[b] > mx ? count[b] : mx;
+    score += mx;
+  }
+  return score;
+}
+
+int plane_row_stride(const Geo& g) {
+  const TeamPlan py = plane_plan_y(g), pz = plane_plan_z(g);
+  const int base = ypad(g.ny - 1) + 1;
+  int best = base, best_score = 1 << 30;
+  for (int e = 0; e < 16; ++e) {
+    const int rs = base + e;
+    if (plane_lds_bytes(g, rs) > kMaxLds) break;
+    const int sc = plane_conflicts(py, g.nz, rs, true) + plane_conflicts(pz, g.ny, rs, false);
+    if (sc < best_score) {
+      best_score = sc;
+      best = rs;
+    }
+  }
+  return best;
+}
+
+// Lane budget of one line in pass B: a 1024-thread workgroup shared by the
+// lines of one axis.
+static int lane_budget(int nlines) {
+  const int b = 1024 / nlines;
+  return b < 1 ? 1 : b;
+}
+TeamPlan plane_plan_y(const Geo& g) { return make_team_plan(g.ny, lane_budget(g.nz)); }
+TeamPlan plane_plan_z(const Geo& g) { return make_team_plan(g.nz, lane_budget(g.ny)); }
+
+static int plane_team_threads(const Geo& g) {
+  const TeamPlan py = plane_plan_y(g), pz = plane_plan_z(g);
+  const int wy = (g.nz + 64 / py.L - 1) / (64 / py.L);
+  const int wz = (g.ny + 64 / pz.L - 1) / (64 / pz.L);
+  int w = wy > wz ? wy : wz;
+  if (w > 16) w = 16;
+  if (w < 1) w = 1;
+  return 64 * w;
+}
+
 bool launch_shape_ok(const Geo& g) {
   if (g.nx % 4 || g.ny % 2) return false;
   const int yb = xline_rows(g.ny), xt = xline_threads(g), pt = plane_threads(g);
@@ -104,8 +196,10 @@ bool launch_shape_ok(const Geo& g) {
   const bool fft_a = 3 * (yb / 2) * g.nx <= kEpt * xt;       // x-line FFT elements per thread
   const bool load_a = 3 * yb * (g.nx / 4) <= kXItems * xt;    // pass A float4 loads
   const bool point_c = yb * (g.nx / 4) <= 2 * xt;             // pass C float4 runs
-  const bool fft_b = g.ny * g.nz <= kEpt * pt;                // plane FFT elements per thread
-  const bool load_b = g.ny * g.nz / 2 <= kPItems * pt;        // pass B float4 loads
+  const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
+  const bool fft_b = ty.nstages > 0 && tz.nstages > 0;        // wave-team plans exist
+  (void)pt;
+  const bool load_b = plane_lds_bytes(g, plane_row_stride(g)) <= (size_t)kMaxLds;  // plane fits in LDS
   const bool div_ok = g.ny * g.nz < 65536 && 3 * yb * g.nx < 65536;  // FastDiv range
   return fft_a && load_a && point_c && fft_b && load_b && div_ok;
 }
@@ -331,23 +425,75 @@ hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* o
 }
 
 // ---------------------------------------------------------------------------
+// transform tables (float64, rounded once)
+// ---------------------------------------------------------------------------
+static size_t a256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t tables_bytes(const Geo& g) {
+  return a256(sizeof(float2) * g.nx) + a256(sizeof(float2) * g.ny) + a256(sizeof(float2) * g.nz) +
+         a256(sizeof(float) * (g.nx / 2 + 1)) + a256(sizeof(float) * g.ny) +
+         a256(sizeof(float) * g.nz);
+}
+
+Tables tables_at(const Geo& g, void* base) {
+  char* p = static_cast<char*>(base);
+  Tables t;
+  t.twx = reinterpret_cast<float2*>(p); p += a256(sizeof(float2) * g.nx);
+  t.twy = reinterpret_cast<float2*>(p); p += a256(sizeof(float2) * g.ny);
+  t.twz = reinterpret_cast<float2*>(p); p += a256(sizeof(float2) * g.nz);
+  t.sx = reinterpret_cast<float*>(p); p += a256(sizeof(float) * (g.nx / 2 + 1));
+  t.sy = reinterpret_cast<float*>(p); p += a256(sizeof(float) * g.ny);
+  t.sz = reinterpret_cast<float*>(p);
+  return t;
+}
+
+__global__ void k_tables(Geo g, Tables t) {
+  const int n_all = g.nx + g.ny + g.nz + (g.nx / 2 + 1) + g.ny + g.nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_all; i += gridDim.x * blockDim.x) {
+    int k = i;
+    float2* tw = nullptr;
+    float* sv = nullptr;
+    int n = 0;
+    if (k < g.nx) { tw = t.twx; n = g.nx; }
+    else if ((k -= g.nx) < g.ny) { tw = t.twy; n = g.ny; }
+    else if ((k -= g.ny) < g.nz) { tw = t.twz; n = g.nz; }
+    else if ((k -= g.nz) < g.nx / 2 + 1) { sv = t.sx; n = g.nx; }
+    else if ((k -= g.nx / 2 + 1) < g.ny) { sv = t.sy; n = g.ny; }
+    else { k -= g.ny; sv = t.sz; n = g.nz; }
+    if (tw) {
+      double sn, cs;
+      sincospi(-2.0 * (double)k / (double)n, &sn, &cs);
+      tw[k] = make_float2((float)cs, (float)sn);
+    } else {
+      const double h = sinpi((double)k / (double)n);
+      sv[k] = (float)(4.0 * h * h);
+    }
+  }
+}
+
+hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st) {
+  hipLaunchKernelGGL(k_tables, dim3(4), dim3(256), 0, st, g, t);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // pass A: t -> packed x half spectrum
 // X layout: X[((c * nx/2 + p) * nz + z) * ny + y], p < nx/2; p = 0 holds
 // (DC, Nyquist) of the real row as one complex value.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd,
+__global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int ls,
+                                                const float2* __restrict__ twx,
                                                 const float* __restrict__ s1,
                                                 const float* __restrict__ s2, float gamma,
                                                 float2* __restrict__ X) {
   extern __shared__ float2 lds[];
   const int nx = g.nx, nh = g.nx / 2, q4 = g.nx / 4;
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
-  const int ls = nx + 1;  // padded line stride (complex)
   float2* tw = lds;
   float2* buf = lds + nx;
   const int y0 = blockIdx.x * yb, z = blockIdx.y;
   const int nthr = blockDim.x;
-  make_twiddles(tw, nx);
+  for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
 
   // load t = s1 + gamma (s1 - s2) as float4 runs along x (all loads first)
   const int items = 3 * yb * q4;
@@ -382,7 +528,7 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd,
                         fmaf(gamma, t.z - u.z, t.z), fmaf(gamma, t.w - u.w, t.w));
       }
       const int line = c * yb2 + (yy >> 1);
-      float* d = bf + 2 * (line * ls + 4 * x4) + (yy & 1);
+      float* d = bf + 2 * (line * ls + lpad<XL_PADSH>(4 * x4)) + (yy & 1);
       d[0] = t.x;
       d[2] = t.y;
       d[4] = t.z;
@@ -390,7 +536,7 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd,
     }
   }
   __syncthreads();
-  fft_lines<kEpt, false>(buf, tw, px, xd.lines, 1, ls);
+  fft_lines<kEpt, false, XL_LINE_FAST, XL_PADSH>(buf, tw, px, xd.lines, 1, ls);
 
   // split into the two rows' half spectra and store (row pairs contiguous)
   const int nout = 3 * nh * yb2;
@@ -402,29 +548,32 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd,
     const float2* Z = buf + (c * yb2 + yp) * ls;
     float4 o;
     if (k == 0) {
-      const float2 z0 = Z[0], zn = Z[nh];
-      o = make_float4(z0.x, zn.x, z0.y, zn.y);
+      // DC and Nyquist bins of the two rows are real: planes 0 and nh
+      const float2 z0 = Z[0], zn = Z[lpad<XL_PADSH>(nh)];
+      o = make_float4(z0.x, 0.f, z0.y, 0.f);
+      float2* dn = X + ((size_t)(c * (nh + 1) + nh) * g.nz + z) * g.ny + y0 + 2 * yp;
+      *reinterpret_cast<float4*>(dn) = make_float4(zn.x, 0.f, zn.y, 0.f);
     } else {
-      const float2 zk = Z[k], zm = Z[nx - k];
+      const float2 zk = Z[lpad<XL_PADSH>(k)], zm = Z[lpad<XL_PADSH>(nx - k)];
       // a = (Zk + conj(Zm)) / 2 ; b = -i (Zk - conj(Zm)) / 2
       o = make_float4(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y), 0.5f * (zk.y + zm.y),
                       -0.5f * (zk.x - zm.x));
     }
-    float2* dst = X + ((size_t)(c * nh + k) * g.nz + z) * g.ny + y0 + 2 * yp;
+    float2* dst = X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y0 + 2 * yp;
     *reinterpret_cast<float4*>(dst) = o;
   }
 }
 
 static size_t pass_a_lds(const Geo& g) {
   const int yb = xline_rows(g.ny);
-  return sizeof(float2) * ((size_t)g.nx + (size_t)3 * (yb / 2) * (g.nx + 1));
+  return sizeof(float2) * ((size_t)g.nx + (size_t)3 * (yb / 2) * xline_stride(g.nx));
 }
 
-hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const float* s1, const float* s2,
-                         float gamma, float2* X, hipStream_t st) {
+hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
+                         const float* s2, float gamma, float2* X, hipStream_t st) {
   const int yb = xline_rows(g.ny);
   hipLaunchKernelGGL(k_pass_a, dim3(g.ny / yb, g.nz), dim3(xline_threads(g)), pass_a_lds(g), st,
-                     g, px, make_xdivs(g), s1, s2, gamma, X);
+                     g, px, make_xdivs(g), xline_stride(g.nx), t.twx, s1, s2, gamma, X);
   return hipGetLastError();
 }
 
@@ -435,117 +584,244 @@ __device__ __forceinline__ float spectral_mult(float k0, float lambda, float the
                                                float inv_v) {
   float kn = k0;
   for (int i = 1; i < order; ++i) kn *= k0;
-  return theta / (theta + lambda * kn) * inv_v;
+  return theta * inv_v * __builtin_amdgcn_rcpf(theta + lambda * kn);
 }
 
-__global__ void __launch_bounds__(1024) k_pass_b(Geo g, FftPlan py, FftPlan pz, XDivs xd,
-                                                 float2* __restrict__ X, float lambda, float theta,
-                                                 int order) {
+// Stage schedules of pass B.  PlansRT reads the (host-made) plans from LDS
+// and dispatches every stage's radix at run time; PlansCT<NY, NZ> has the
+// same plans as compile-time constants, so only the radices a size uses are
+// compiled into its kernel (small code, constant index arithmetic).
+struct PlansRT {
+  const TeamPlan* py;
+  const TeamPlan* pz;
+  const TeamPlan* pzi;
+  __device__ int ly() const { return py->L; }
+  __device__ int lz() const { return pz->L; }
+  template <bool INV>
+  __device__ void y_all(float2* line, const float2* tw, int tl) const {
+    for (int st = 0; st < py->nstages; ++st)
+      team_stage_any<kTeamEpt, INV, 4>(line, tw, py->st[st], py->L, tl, 1);
+  }
+  __device__ void z_fused(float2* line, const float2* tw, int tl, int es,
+                          const SpectralMult& mult) const {
+    for (int st = 0; st + 1 < pz->nstages; ++st)
+      team_stage_any<kTeamEpt, false, 0>(line, tw, pz->st[st], pz->L, tl, es);
+    team_fused_any<kTeamEpt, 0>(line, tw, pz->st[pz->nstages - 1], pzi->st[0], pz->L, tl, es, mult);
+    for (int st = 1; st < pzi->nstages; ++st)
+      team_stage_any<kTeamEpt, true, 0>(line, tw, pzi->st[st], pzi->L, tl, es);
+  }
+};
+
+constexpr int lane_budget_ce(int nlines) { return 1024 / nlines < 1 ? 1 : 1024 / nlines; }
+
+template <int NY, int NZ>
+struct PlansCT {
+  static constexpr TeamPlan PY = make_team_plan_ce(NY, lane_budget_ce(NZ));
+  static constexpr TeamPlan PZ = make_team_plan_ce(NZ, lane_budget_ce(NY));
+  static constexpr TeamPlan PZI = reverse_team_plan_ce(PZ);
+  static_assert(PY.nstages > 0 && PZ.nstages > 0, "no wave-team plan for this size");
+  __device__ int ly() const { return PY.L; }
+  __device__ int lz() const { return PZ.L; }
+
+  template <int WHICH, bool INV, int PADSH, int S, int SEND>
+  __device__ static void stages(float2* line, const float2* tw, int tl, int es) {
+    if constexpr (S < SEND) {
+      constexpr TeamPlan P = WHICH == 0 ? PY : (WHICH == 1 ? PZ : PZI);
+      constexpr FftStage st = P.st[S];
+      team_stage<st.R, P.n / P.L, INV, PADSH>(line, tw, st, P.L, tl, es);
+      stages<WHICH, INV, PADSH, S + 1, SEND>(line, tw, tl, es);
+    }
+  }
+  template <bool INV>
+  __device__ void y_all(float2* line, const float2* tw, int tl) const {
+    stages<0, INV, 4, 0, PY.nstages>(line, tw, tl, 1);
+  }
+  __device__ void z_fused(float2* line, const float2* tw, int tl, int es,
+                          const SpectralMult& mult) const {
+    stages<1, false, 0, 0, PZ.nstages - 1>(line, tw, tl, es);
+    constexpr FftStage sf = PZ.st[PZ.nstages - 1];
+    constexpr FftStage si = PZI.st[0];
+    team_fused<sf.R, PZ.n / PZ.L, 0>(line, tw, sf, si, PZ.L, tl, es, mult);
+    stages<2, true, 0, 1, PZI.nstages>(line, tw, tl, es);
+  }
+};
+
+// NY = NZ = 0: any size (run-time plans); otherwise the sizes are fixed.
+template <int NY, int NZ>
+__global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan pz0, TeamPlan pzi0,
+                                                 XDivs xd, int rs, Tables tg, float2* __restrict__ X,
+                                                 float lambda, float theta, int order) {
   extern __shared__ float2 lds[];
-  const int ny = g.ny, nz = g.nz, nh = g.nx / 2;
-  const int rs = ny + 1;  // padded row stride of the [z][y] plane
+  // run-time plans are indexed by stage: keep them in LDS
+  __shared__ __align__(16) unsigned char plan_mem[NY == 0 ? 3 * sizeof(TeamPlan) : 16];
+  TeamPlan* plans = reinterpret_cast<TeamPlan*>(plan_mem);
+  using Pol = typename std::conditional<NY == 0, PlansRT, PlansCT<NY, NZ>>::type;
+  Pol pol{};
+  if constexpr (NY == 0) pol = PlansRT{plans, plans + 1, plans + 2};
+  // plane element (z, y) at z * rs + y + y / 16 (host-chosen rs)
+  const int ny = NY ? NY : g.ny, nz = NZ ? NZ : g.nz, np = g.nx / 2 + 1;
   const int nthr = blockDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = nthr >> 6;
   float2* twy = lds;
   float2* twz = twy + ny;
   float* sy = reinterpret_cast<float*>(twz + nz);
   float* sz = sy + ny;
   float2* buf = reinterpret_cast<float2*>(sz + nz + ((ny + nz) & 1));  // keep 8-byte alignment
   const int p = blockIdx.x, c = blockIdx.y;
-  float2* plane = X + (size_t)(c * nh + p) * nz * ny;
-  const int n = ny * nz, n2 = n / 2;
+  float2* plane = X + (size_t)(c * np + p) * nz * ny;
+  const float4* plane4 = reinterpret_cast<const float4*>(plane);
+  const float inv_v = 1.0f / (float)g.V;
+  const int nlw_y = 64 / (NY ? PlansCT<NY ? NY : 32, NZ ? NZ : 32>::PY.L : py0.L);
 
-  // issue every global load of the plane first (two complex per float4)
-  float4 v[kPItems];
+  // Rows of the y transform are owned by wavefronts: lines [l0, l0 + nlw_y)
+  // with l0 = wave * nlw_y (+ multiples of nwaves * nlw_y).  Issue the loads
+  // of the first group and of the tables together, then store both to LDS.
+  auto load_rows = [&](int l0, int b0, float4* v) {
+    const int rows = (nz - l0 < nlw_y) ? nz - l0 : nlw_y;
+    const int items = rows * (ny / 2);  // float4 = two complex of one row
 #pragma unroll
-  for (int it = 0; it < kPItems; ++it) {
-    const int i2 = threadIdx.x + it * nthr;
-    if (i2 < n2) v[it] = reinterpret_cast<const float4*>(plane)[i2];
-  }
-  make_twiddles(twy, ny);
-  make_twiddles(twz, nz);
-  // symbol pieces 2 - 2 cos(2 pi q / n) = 4 sin^2(pi q / n), float64 then rounded
-  for (int i = threadIdx.x; i < ny + nz; i += nthr) {
-    if (i < ny) {
-      const double s = sinpi((double)i / ny);
-      sy[i] = (float)(4.0 * s * s);
-    } else {
-      const double s = sinpi((double)(i - ny) / nz);
-      sz[i - ny] = (float)(4.0 * s * s);
+    for (int it = 0; it < kPItems; ++it) {
+      const int idx = b0 + lane + it * 64;
+      if (idx < items) v[it] = plane4[l0 * (ny / 2) + idx];
     }
-  }
+    return items;
+  };
+  auto store_rows = [&](int l0, int b0, int items, const float4* v) {
 #pragma unroll
-  for (int it = 0; it < kPItems; ++it) {
-    const int i2 = threadIdx.x + it * nthr;
-    if (i2 < n2) {
-      const int i = 2 * i2;
-      const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;  // ny even: same row
-      buf[zz * rs + yy] = make_float2(v[it].x, v[it].y);
-      buf[zz * rs + yy + 1] = make_float2(v[it].z, v[it].w);
+    for (int it = 0; it < kPItems; ++it) {
+      const int idx = b0 + lane + it * 64;
+      if (idx < items) {
+        const int i = 2 * idx;
+        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;  // yy even
+        float2* d = buf + (l0 + zz) * rs + lpad<4>(yy);
+        d[0] = make_float2(v[it].x, v[it].y);
+        d[1] = make_float2(v[it].z, v[it].w);
+      }
+    }
+  };
+  {
+    float2 t2 = make_float2(0.f, 0.f);
+    float t1 = 0.f;
+    const int ti = threadIdx.x;
+    if (ti < ny) {
+      t2 = tg.twy[ti];
+      t1 = tg.sy[ti];
+    } else if (ti < ny + nz) {
+      t2 = tg.twz[ti - ny];
+      t1 = tg.sz[ti - ny];
+    }
+    float4 v[kPItems];
+    const int l0 = wave * nlw_y;
+    int items = 0;
+    if (l0 < nz) items = load_rows(l0, 0, v);
+    if (NY == 0 && threadIdx.x == 0) {
+      plans[0] = py0;
+      plans[1] = pz0;
+      plans[2] = pzi0;
+    }
+    if (ti < ny) {
+      twy[ti] = t2;
+      sy[ti] = t1;
+    } else if (ti < ny + nz) {
+      twz[ti - ny] = t2;
+      sz[ti - ny] = t1;
+    }
+    for (int i = ny + nz + threadIdx.x; i < 2 * (ny + nz); i += nthr) {  // blocks narrower than ny + nz
+      const int k = i - (ny + nz);
+      if (k < ny) {
+        twy[k] = tg.twy[k];
+        sy[k] = tg.sy[k];
+      } else {
+        twz[k - ny] = tg.twz[k - ny];
+        sz[k - ny] = tg.sz[k - ny];
+      }
+    }
+    if (l0 < nz) {
+      store_rows(l0, 0, items, v);
+      for (int b0 = kPItems * 64; b0 < items; b0 += kPItems * 64) {
+        load_rows(l0, b0, v);
+        store_rows(l0, b0, items, v);
+      }
     }
   }
   __syncthreads();
-  fft_lines<kEpt, false>(buf, twy, py, xd.nz, 1, rs);  // along y (nz lines)
-  fft_lines<kEpt, false>(buf, twz, pz, xd.ny, rs, 1);  // along z (ny lines)
 
-  const float inv_v = 1.0f / (float)g.V;
-  if (p > 0) {
-    const double sxd = sinpi((double)p / g.nx);
-    const float sx = (float)(4.0 * sxd * sxd);
-    for (int i = threadIdx.x; i < n; i += nthr) {
-      const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
-      const float m = spectral_mult(sx + sy[yy] + sz[zz], lambda, theta, order, inv_v);
-      float2& e = buf[zz * rs + yy];
-      e = cscale(e, m);
-    }
-    __syncthreads();
-  } else {
-    // Packed plane P = Z0 + i Zn of two real signals (x DC and x Nyquist rows):
-    // result m0 Z0 + i mn Zn = (m0 + mn)/2 P + (m0 - mn)/2 conj(P(-q, -r)).
-    float2 res[kEpt];
-#pragma unroll
-    for (int it = 0; it < kEpt; ++it) {
-      const int i = threadIdx.x + it * nthr;
-      if (i < n) {
-        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
-        const int zr = (zz == 0) ? 0 : nz - zz, yr = (yy == 0) ? 0 : ny - yy;
-        const float2 P = buf[zz * rs + yy];
-        const float2 Pt = cconj(buf[zr * rs + yr]);
-        const float m0 = spectral_mult(sy[yy] + sz[zz], lambda, theta, order, inv_v);
-        const float mn = spectral_mult(4.0f + sy[yy] + sz[zz], lambda, theta, order, inv_v);
-        const float A = 0.5f * (m0 + mn), B = 0.5f * (m0 - mn);
-        res[it] = make_float2(A * P.x + B * Pt.x, A * P.y + B * Pt.y);
+  // --- along y ---------------------------------------------------------------
+  {
+    const int nlw = nlw_y, li = lane % nlw, tl = lane / nlw;
+    for (int l0 = wave * nlw; l0 < nz; l0 += nwaves * nlw) {
+      if (l0 != wave * nlw) {  // further row groups of this wavefront
+        float4 v[kPItems];
+        const int items = (nz - l0 < nlw ? nz - l0 : nlw) * (ny / 2);
+        for (int b0 = 0; b0 < items; b0 += kPItems * 64) {
+          load_rows(l0, b0, v);
+          store_rows(l0, b0, items, v);
+        }
+        wave_lds_fence();
       }
+      const int l = l0 + li;
+      if (l < nz) pol.template y_all<false>(buf + l * rs, twy, tl);
     }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < kEpt; ++it) {
-      const int i = threadIdx.x + it * nthr;
-      if (i < n) {
-        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
-        buf[zz * rs + yy] = res[it];
-      }
-    }
-    __syncthreads();
   }
-  fft_lines<kEpt, true>(buf, twz, pz, xd.ny, rs, 1);
-  fft_lines<kEpt, true>(buf, twy, py, xd.nz, 1, rs);
-  for (int i2 = threadIdx.x; i2 < n2; i2 += nthr) {
-    const int i = 2 * i2;
-    const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
-    const float2 a = buf[zz * rs + yy], b = buf[zz * rs + yy + 1];
-    reinterpret_cast<float4*>(plane)[i2] = make_float4(a.x, a.y, b.x, b.y);
+  __syncthreads();
+
+  // --- along z: forward, spectral multiply, inverse, fused per column ------
+  {
+    const int nlw = 64 / pol.lz(), li = lane % nlw, tl = lane / nlw;
+    const float sx = tg.sx[p];
+    for (int l0 = wave * nlw; l0 < ny; l0 += nwaves * nlw) {
+      const int q = l0 + li;
+      if (q < ny) {
+        const SpectralMult mult{sz, sx + sy[q], lambda, theta, inv_v, order};
+        pol.z_fused(buf + lpad<4>(q), twz, tl, rs, mult);
+      }
+    }
+  }
+  __syncthreads();
+
+  // --- inverse along y, every wavefront stores its own rows ----------------
+  {
+    const int nlw = nlw_y, li = lane % nlw, tl = lane / nlw;
+    float4* out4 = reinterpret_cast<float4*>(plane);
+    for (int l0 = wave * nlw; l0 < nz; l0 += nwaves * nlw) {
+      const int l = l0 + li;
+      if (l < nz) pol.template y_all<true>(buf + l * rs, twy, tl);
+      wave_lds_fence();
+      const int items = (nz - l0 < nlw ? nz - l0 : nlw) * (ny / 2);
+      for (int idx = lane; idx < items; idx += 64) {
+        const int i = 2 * idx;
+        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
+        const float2* sp = buf + (l0 + zz) * rs + lpad<4>(yy);
+        const float2 a = sp[0], b = sp[1];
+        out4[l0 * (ny / 2) + idx] = make_float4(a.x, a.y, b.x, b.y);
+      }
+    }
   }
 }
 
-static size_t pass_b_lds(const Geo& g) {
-  return sizeof(float2) * (size_t)(g.ny + g.nz) + sizeof(float) * (size_t)(g.ny + g.nz + 1) +
-         sizeof(float2) * (size_t)g.nz * (g.ny + 1);
-}
+static size_t pass_b_lds(const Geo& g) { return plane_lds_bytes(g, plane_row_stride(g)); }
 
-hipError_t launch_pass_b(const Geo& g, const FftPlan& py, const FftPlan& pz, float2* X,
-                         float lambda, float theta, int order, hipStream_t st) {
-  hipLaunchKernelGGL(k_pass_b, dim3(g.nx / 2, 3), dim3(plane_threads(g)), pass_b_lds(g), st, g,
-                     py, pz, make_xdivs(g), X, lambda, theta, order);
+hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
+                         int order, hipStream_t st) {
+  const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
+  const dim3 grid(g.nx / 2 + 1, 3), block(plane_team_threads(g));
+  const size_t lds = pass_b_lds(g);
+  const XDivs xd = make_xdivs(g);
+  const int rs = plane_row_stride(g);
+  const TeamPlan tzi = reverse_team_plan(tz);
+#define NADMM_PASS_B(NY_, NZ_)                                                                 \
+  if (g.ny == NY_ && g.nz == NZ_) {                                                            \
+    hipLaunchKernelGGL((k_pass_b<NY_, NZ_>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, \
+                       lambda, theta, order);                                                  \
+    return hipGetLastError();                                                                  \
+  }
+  NADMM_PASS_B(32, 32) NADMM_PASS_B(32, 64) NADMM_PASS_B(32, 96) NADMM_PASS_B(32, 128)
+  NADMM_PASS_B(64, 32) NADMM_PASS_B(64, 64) NADMM_PASS_B(64, 96) NADMM_PASS_B(64, 128)
+  NADMM_PASS_B(96, 32) NADMM_PASS_B(96, 64) NADMM_PASS_B(96, 96) NADMM_PASS_B(96, 128)
+  NADMM_PASS_B(128, 32) NADMM_PASS_B(128, 64) NADMM_PASS_B(128, 96) NADMM_PASS_B(128, 128)
+#undef NADMM_PASS_B
+  hipLaunchKernelGGL((k_pass_b<0, 0>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, lambda,
+                     theta, order);
   return hipGetLastError();
 }
 
@@ -562,11 +838,11 @@ __device__ __forceinline__ void f4set(float4& v, int e, float s) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, PassCArgs a) {
+__global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
+                                                const float2* __restrict__ twx, PassCArgs a) {
   extern __shared__ float2 lds[];
   const int nx = g.nx, nh = g.nx / 2, q4 = g.nx / 4;
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
-  const int ls = nx + 1;
   const int nthr = blockDim.x;
   float2* tw = lds;
   float2* buf = lds + nx;
@@ -574,7 +850,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, Pas
 
   // unpack two rows' half spectra into one complex row: Z = Xa + i Xb
   const int nin = 3 * nh * yb2;
-  float4 in[kXItems];
+  float4 in[kXItems], inn[kXItems];
 #pragma unroll
   for (int it = 0; it < kXItems; ++it) {
     const int idx = threadIdx.x + it * nthr;
@@ -583,11 +859,13 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, Pas
       const int yp = idx - ck * yb2;
       const int c = (int)fdiv((uint32_t)ck, xd.nh);
       const int k = ck - c * nh;
-      in[it] = *reinterpret_cast<const float4*>(a.X + ((size_t)(c * nh + k) * g.nz + z) * g.ny +
-                                                y0 + 2 * yp);
+      const float2* src = a.X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y0 + 2 * yp;
+      in[it] = *reinterpret_cast<const float4*>(src);
+      if (k == 0)  // the Nyquist plane
+        inn[it] = *reinterpret_cast<const float4*>(src + (size_t)nh * g.nz * g.ny);
     }
   }
-  make_twiddles(tw, nx);
+  for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
 #pragma unroll
   for (int it = 0; it < kXItems; ++it) {
     const int idx = threadIdx.x + it * nthr;
@@ -599,16 +877,18 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, Pas
       float2* Z = buf + (c * yb2 + yp) * ls;
       const float4 q = in[it];  // (a.re, a.im, b.re, b.im)
       if (k == 0) {
+        // real DC and Nyquist bins of the two rows (imaginary parts are zero)
+        const float4 qn = inn[it];
         Z[0] = make_float2(q.x, q.z);
-        Z[nh] = make_float2(q.y, q.w);
+        Z[lpad<XL_PADSH>(nh)] = make_float2(qn.x, qn.z);
       } else {
-        Z[k] = make_float2(q.x - q.w, q.y + q.z);
-        Z[nx - k] = make_float2(q.x + q.w, q.z - q.y);
+        Z[lpad<XL_PADSH>(k)] = make_float2(q.x - q.w, q.y + q.z);
+        Z[lpad<XL_PADSH>(nx - k)] = make_float2(q.x + q.w, q.z - q.y);
       }
     }
   }
   __syncthreads();
-  fft_lines<kEpt, true>(buf, tw, px, xd.lines, 1, ls);
+  fft_lines<kEpt, true, XL_LINE_FAST, XL_PADSH>(buf, tw, px, xd.lines, 1, ls);
 
   const float* bf = reinterpret_cast<const float*>(buf);
   const int nitems = yb * q4;  // float4 runs of 4 voxels along x
@@ -623,7 +903,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, Pas
       gi[it] = (z * g.ny + y0 + yy) * nx + 4 * x4;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float* rowp = bf + 2 * ((c * yb2 + (yy >> 1)) * ls + 4 * x4) + (yy & 1);
+        const float* rowp = bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<XL_PADSH>(4 * x4)) + (yy & 1);
         yv[it][c] = make_float4(rowp[0], rowp[2], rowp[4], rowp[6]);
       }
     }
@@ -729,17 +1009,18 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, Pas
   }
 }
 
-hipError_t launch_pass_c(const Geo& g, const FftPlan& px, PassCMode mode, const PassCArgs& a,
-                         hipStream_t st) {
+hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
+                         const PassCArgs& a, hipStream_t st) {
   const int yb = xline_rows(g.ny);
   const dim3 grid(g.ny / yb, g.nz), block(xline_threads(g));
   const size_t lds = pass_a_lds(g);
   const XDivs xd = make_xdivs(g);
+  const int ls = xline_stride(g.nx);
   switch (mode) {
-    case kOutY: hipLaunchKernelGGL(k_pass_c<kOutY>, grid, block, lds, st, g, px, xd, a); break;
-    case kIter: hipLaunchKernelGGL(k_pass_c<kIter>, grid, block, lds, st, g, px, xd, a); break;
-    case kFinalWB: hipLaunchKernelGGL(k_pass_c<kFinalWB>, grid, block, lds, st, g, px, xd, a); break;
-    default: hipLaunchKernelGGL(k_pass_c<kCompose>, grid, block, lds, st, g, px, xd, a); break;
+    case kOutY: hipLaunchKernelGGL(k_pass_c<kOutY>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
+    case kIter: hipLaunchKernelGGL(k_pass_c<kIter>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
+    case kFinalWB: hipLaunchKernelGGL(k_pass_c<kFinalWB>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
+    default: hipLaunchKernelGGL(k_pass_c<kCompose>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
   }
   return hipGetLastError();
 }
