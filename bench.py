@@ -24,9 +24,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # Algorithmic bytes per voxel of each kernel kind (inputs read once, outputs
 # written once; float32 fields, packed half spectrum = 4 B per component).
 BYTES_PER_VOXEL = {
-    "pass_a_fwd_x": None,        # 36 with extrapolation (reads s^k, s^{k-1}), 24 without
+    "pass_a_fwd_x": 24.0,        # s^0 12, write the half spectrum 12 (once per warping)
     "pass_b_yz_solve": 24.0,     # read + write the 3-component half spectrum
-    "pass_c_iter": 64.0,         # spectrum 12 + s^k, s^{k-1} 24 + J 12 + r 4, write s 12
+    "pass_ca_iter": 76.0,        # spectrum 12 + s^k, s^{k-1} 24 + J 12 + r 4, write s 12 + spectrum 12
     "pass_c_compose": 44.0,      # spectrum 12 + u gather 12 + image gather 4, write u 12 + I^w 4
     "grad_resid": 36.0,          # I^w 4 + I0 4, write J 12 + r 4 + s^0 12
     "warp": 20.0,                # u 12 + image 4, write 4
@@ -130,19 +130,16 @@ def main():
     kernels = {}
     for k, (n, ms) in prof.items():
         kernels[k] = {"launches_per_step": n / args.profile_steps, "avg_us": 1e3 * ms / n}
-    n_iter = w["outer"] * (w["iters"] - 1)
-    per_iter_us = sum(1e3 * prof[k][1] for k in ("pass_a_fwd_x", "pass_b_yz_solve", "pass_c_iter")
-                      if k in prof) / max(1, args.profile_steps * n_iter)
-    # pass A runs with extrapolation (iters-1 per warping) and without (1 per warping)
-    na = w["iters"] - 1
-    BYTES_PER_VOXEL["pass_a_fwd_x"] = (36.0 * na + 24.0) / (na + 1)
+    # one ADMM iteration = the fused pass C + A and one pass B
+    per_iter_us = (1e3 * prof["pass_ca_iter"][1] / prof["pass_ca_iter"][0] +
+                   1e3 * prof["pass_b_yz_solve"][1] / prof["pass_b_yz_solve"][0])
     # dominant kernel: largest share of the instrumented step; its duration is
     # re-measured by replaying it back to back between two HIP events on the
     # same stream (per-launch event brackets add launch gaps)
     dom = max((k for k in api.REPLAY_KINDS if k in prof), key=lambda k: prof[k][1])
     step()
     avg_ms = api.profile_replay(shp, dom, 200, w["lam"], w["theta"], w["order"], ws)
-    bpv = 36.0 if dom == "pass_a_fwd_x" else BYTES_PER_VOXEL[dom]
+    bpv = BYTES_PER_VOXEL[dom]
     avg_s = avg_ms / 1e3
     achieved = bpv * V / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -171,9 +171,12 @@ int nadmm_profile_read(int max, const char** names, int64_t* counts, double* tot
  * times back to back (1 <= reps <= 10000) on the buffers that a preceding
  * nadmm_register call with the same dims and params left in `workspace`,
  * between two HIP events on `stream`, waits for them and writes the mean
- * milliseconds per launch to host *avg_ms.  kind: 0 = forward x pass with
- * extrapolation, 1 = y-z spectral pass, 2 = inverse x pass with the data
- * step.  The replayed launches overwrite the workspace's iteration state. */
+ * milliseconds per launch to host *avg_ms.  kind: 0 = forward x pass of a
+ * warping's first solve, 1 = y-z spectral pass, 2 = the fused x pass of the
+ * iteration loop (inverse x transform, data step and new state, extrapolation
+ * and forward x transform of the next solve's input; replayed with zero
+ * extrapolation weights so that the state stays bounded).  The replayed
+ * launches overwrite the workspace's iteration state. */
 nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t kind, int32_t reps,
                                   void* workspace, size_t workspace_bytes, void* stream,
                                   double* avg_ms);

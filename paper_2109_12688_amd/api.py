@@ -178,7 +178,7 @@ def jacobian(disp: torch.Tensor, want_det: bool = False, ws: torch.Tensor | None
     return stats, nneg, det
 
 
-REPLAY_KINDS = {"pass_a_fwd_x": 0, "pass_b_yz_solve": 1, "pass_c_iter": 2}
+REPLAY_KINDS = {"pass_a_fwd_x": 0, "pass_b_yz_solve": 1, "pass_ca_iter": 2}
 
 
 def profile_replay(vol_shape, kind: str, reps: int, lam: float, theta: float, order: int,

@@ -35,11 +35,11 @@ nadmm_status fail(nadmm_status s, const char* fmt, ...) {
 // ---- optional per-kernel event timing -----------------------------------
 enum KernelKind {
   KK_FILL, KK_SCALE, KK_WARP, KK_GRAD, KK_ADMM_INIT, KK_PASS_A, KK_PASS_B, KK_PASS_C_OUT,
-  KK_PASS_C_ITER, KK_PASS_C_WB, KK_PASS_C_COMPOSE, KK_COMPOSE, KK_JACOBIAN, KK_COUNT
+  KK_PASS_CA_ITER, KK_PASS_C_WB, KK_PASS_C_COMPOSE, KK_COMPOSE, KK_JACOBIAN, KK_COUNT
 };
 const char* const kKindNames[KK_COUNT] = {
     "fill", "scale", "warp", "grad_resid", "admm_init", "pass_a_fwd_x", "pass_b_yz_solve",
-    "pass_c_out", "pass_c_iter", "pass_c_final_wb", "pass_c_compose", "compose", "jacobian"};
+    "pass_c_out", "pass_ca_iter", "pass_c_final_wb", "pass_c_compose", "compose", "jacobian"};
 
 struct ProfRecord {
   int kind;
@@ -203,21 +203,23 @@ hipError_t spectral_ab(const Geo& g, const Plans& pl, const Tables& tb, const na
   });
 }
 
-// The ADMM loop of one warping, in the two-field form: s^0 already in S1.
-// Runs iterations k = 1 .. iters-1 and leaves s^{iters-1} in *cur.
+// The ADMM loop of one warping in the two-field form, with s^0 already in
+// *cur.  Runs iterations k = 1 .. iters-1 (each: pass C of S t^k fused with
+// pass A of the next solve's input, then pass B).  On return *cur holds
+// s^{iters-1} and X the pass-B output for S s^{iters-1}, ready for the
+// warping's final pass C.
 nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
                              const nadmm_params* p, const float* J, const float* r, float*& cur,
                              float*& prev, float2* X, float* v_last, hipStream_t st) {
   const std::vector<double> gam = nesterov_gammas(p->iters);
+  HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st));  // gamma_0 = 0: t = s^0
   for (int k = 1; k < p->iters; ++k) {
-    const float gk = (float)gam[k - 1];
-    const float* s2 = (k == 1) ? nullptr : prev;  // gamma_0 = 0: s^{-1} never read
-    HIP_TRY(spectral_ab(g, pl, tb, p, cur, s2, gk, X, st));
     PassCArgs a{};
     a.X = X;
     a.s1 = cur;
-    a.s2 = s2;
-    a.gamma = gk;
+    a.s2 = (k == 1) ? nullptr : prev;  // s^{-1} is never read
+    a.gamma = (float)gam[k - 1];
+    a.gamma_next = (k + 1 < p->iters) ? (float)gam[k] : 0.0f;  // the final solve takes s as is
     a.J = J;
     a.r = r;
     a.theta = (float)p->theta;
@@ -225,7 +227,10 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     a.data_term = p->data_term;
     a.out = prev;  // s^k overwrites s^{k-2} voxel by voxel
     a.v_out = (k == p->iters - 1) ? v_last : nullptr;
-    HIP_TRY(timed(KK_PASS_C_ITER, st, [&] { return launch_pass_c(g, pl.x, tb, kIter, a, st); }));
+    HIP_TRY(timed(KK_PASS_CA_ITER, st, [&] { return launch_pass_c(g, pl.x, tb, kIterFwd, a, st); }));
+    HIP_TRY(timed(KK_PASS_B, st, [&] {
+      return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
+    }));
     float* tmp = cur;
     cur = prev;
     prev = tmp;
@@ -315,7 +320,6 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p, const float* fi
     float* prev = S2;
     CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, nullptr, st));
     // final w = S s^{K-1}, composed onto the displacement
-    HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st));
     PassCArgs a{};
     a.X = X;
     a.out = dst_of(c);
@@ -354,7 +358,6 @@ nadmm_status nadmm_admm(nadmm_dims d, const nadmm_params* p, const float* J, con
   float* cur = S1;
   float* prev = S2;
   CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, v_out, st));
-  HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st));
   PassCArgs a{};
   a.X = X;
   a.s1 = cur;
@@ -476,13 +479,16 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   float* S1 = at<float>(workspace, L.s1);
   float* S2 = at<float>(workspace, L.s2);
   float2* X = at<float2>(workspace, L.X);
-  const float gamma = (float)nesterov_gammas(3)[2];
   const Tables tb = tables_at(g, at<char>(workspace, L.tab));
+  // kind 2 replays the fused pass C + A with zero extrapolation weights (the
+  // same loads, arithmetic and stores) so that the repeated state stays
+  // bounded without pass B in between
   PassCArgs a{};
   a.X = X;
   a.s1 = S1;
   a.s2 = S2;
-  a.gamma = gamma;
+  a.gamma = 0.0f;
+  a.gamma_next = 0.0f;
   a.J = J;
   a.r = r;
   a.theta = (float)p->theta;
@@ -490,9 +496,9 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   a.data_term = p->data_term;
   a.out = S2;
   auto launch = [&]() -> hipError_t {
-    if (kind == 0) return launch_pass_a(g, pl.x, tb, S1, S2, gamma, X, st);
+    if (kind == 0) return launch_pass_a(g, pl.x, tb, S1, nullptr, 0.0f, X, st);
     if (kind == 1) return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
-    return launch_pass_c(g, pl.x, tb, kIter, a, st);
+    return launch_pass_c(g, pl.x, tb, kIterFwd, a, st);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
@@ -504,8 +510,8 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   if (err == hipSuccess) err = hipEventSynchronize(e1);
   float ms = 0.f;
   if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   if (err != hipSuccess) return fail(NADMM_ERR_HIP, "replay: %s", hipGetErrorString(err));
   *avg_ms = (double)ms / reps;
   return NADMM_OK;

@@ -279,6 +279,115 @@ __device__ void fft_lines(float2* buf, const float2* tw, const FftPlan& plan, co
   }
 }
 
+// Stockham plans fixed at compile time: fewest stages for n with radices
+// from {16, 12, 8, 6, 4, 3, 2}, and among plans with equally few stages the
+// one with the largest leading radices.  The host builds its run-time plans
+// from the same search.
+struct StockhamRadices {
+  int nstages = -1;
+  int R[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+constexpr bool stockham_search_ce(int m, int depth, int* out) {
+  if (m == 1) return depth == 0;
+  if (depth == 0) return false;
+  const int radices[7] = {16, 12, 8, 6, 4, 3, 2};
+  for (int i = 0; i < 7; ++i) {
+    const int r = radices[i];
+    if (m % r == 0 && stockham_search_ce(m / r, depth - 1, out + 1)) {
+      out[0] = r;
+      return true;
+    }
+  }
+  return false;
+}
+
+constexpr StockhamRadices stockham_radices_ce(int n) {
+  StockhamRadices p{};
+  for (int depth = 1; depth <= 8; ++depth) {
+    int rad[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (stockham_search_ce(n, depth, rad)) {
+      p.nstages = depth;
+      for (int i = 0; i < depth; ++i) p.R[i] = rad[i];
+      return p;
+    }
+  }
+  return p;
+}
+
+// radix of the stage whose earlier stages span ns elements (0: none)
+constexpr int stockham_radix_at(int n, int ns) {
+  const StockhamRadices p = stockham_radices_ce(n);
+  int span = 1;
+  for (int i = 0; i < p.nstages; ++i) {
+    if (span == ns) return p.R[i];
+    span *= p.R[i];
+  }
+  return 0;
+}
+
+// One radix-R stage of a length-N transform with every index constant but
+// the line count; butterflies of one line on consecutive threads and
+// element e of line l at buf[l * ls + lpad<PADSH>(e)].  The caller
+// guarantees nlines * N / R <= MAXB * blockDim.x.
+template <int R, int NS, int N, int MAXB, bool INV, int PADSH>
+__device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int nlines, int ls) {
+  constexpr int NB = N / R, TWS = N / (NS * R);
+  const uint32_t total = (uint32_t)(NB * nlines);
+  const uint32_t nthr = blockDim.x;
+  float2 v[MAXB][R];
+  int base[MAXB], jj[MAXB];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const uint32_t b = threadIdx.x + i * nthr;
+    if (b < total) {
+      const uint32_t line = b / (uint32_t)NB;
+      const int j = (int)(b - line * NB);
+      base[i] = (int)line * ls;
+      jj[i] = j;
+      const float2* src = buf + base[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = src[lpad<PADSH>(j + r * NB)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const uint32_t b = threadIdx.x + i * nthr;
+    if (b < total) {
+      const int j = jj[i];
+      const int k = (int)((uint32_t)j % (uint32_t)NS);
+      if constexpr (NS > 1) {  // the first stage's twiddles are all 1
+        const int step = k * TWS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * step];
+          if (INV) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[i]);
+      float2* dst = buf + base[i];
+      const int d0 = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[lpad<PADSH>(d0 + r * NS)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full length-N transform of `nlines` lines with the compile-time plan;
+// nlines * N <= EPT * blockDim.x.
+template <int N, int EPT, bool INV, int PADSH, int NS = 1>
+__device__ __forceinline__ void fft_lines_ct(float2* buf, const float2* tw, int nlines, int ls) {
+  if constexpr (NS < N) {
+    constexpr int R = stockham_radix_at(N, NS);
+    static_assert(R > 1, "no Stockham plan for this length");
+    fft_stage_ct<R, NS, N, (EPT + R - 1) / R, INV, PADSH>(buf, tw, nlines, ls);
+    fft_lines_ct<N, EPT, INV, PADSH, NS * R>(buf, tw, nlines, ls);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Wave-team FFTs: every line is transformed by a team of L lanes of ONE
 // wavefront, so the stages of a line need no workgroup barrier; LDS

@@ -65,20 +65,24 @@ Tables tables_at(const Geo& g, void* base);
 hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 
 // Pass C (inverse x transform + pointwise update) output modes.
-enum PassCMode { kOutY = 0, kIter = 1, kFinalWB = 2, kCompose = 3 };
+// kIterFwd: the data step and s^k, followed on the same x-lines by pass A of
+// the next solve (t' = s^k + gamma_next (s^k - s^{k-1}) transformed along x
+// and written back over the spectrum the pass read).
+enum PassCMode { kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3 };
 
 struct PassCArgs {
-  const float2* X;
+  float2* X;         // read; kIterFwd also writes the next half spectrum here
   const float* s1;   // s^{k-1} (iteration), s (final)
   const float* s2;   // s^{k-2} or nullptr when gamma = 0
   float gamma;
+  float gamma_next;  // kIterFwd: extrapolation weight of the next solve's input
   const float* J;
   const float* r;
   float theta;
   float eps;
   int data_term;
-  float* out;        // kOutY: y; kIter: s^k (may alias s2); kFinalWB: w; kCompose: new u
-  float* v_out;      // kIter: optional v^k
+  float* out;        // kOutY: y; kIterFwd: s^k (may alias s2); kFinalWB: w; kCompose: new u
+  float* v_out;      // kIterFwd: optional v^k
   float* b_out;      // kFinalWB: optional b
   const float* u_old;  // kCompose: displacement before this warping
   const float* img;    // kCompose: moving image

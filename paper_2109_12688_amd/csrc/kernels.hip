@@ -13,16 +13,17 @@
 // is then: y = S t (three passes below), a = w_hat - b_hat = 2y - t,
 // v = data step(a), s^{k+1} = v + t - y.  Only s^k and s^{k-1} are stored.
 //
-// S itself is three memory passes per iteration:
-//   pass A  per x-line: t, packed real FFT along x (two real rows as one
-//           complex row), half spectrum with the DC and Nyquist bins of a
-//           row packed into one complex value;
+// S itself is three memory passes:
+//   pass A  per x-line: t, real FFT along x (two real rows as one complex
+//           row), half spectrum of nx/2 + 1 bins scaled by 1 / nx; bins 0
+//           and nx/2 (real) form planes of their own;
 //   pass B  per y-z plane of one x frequency: FFT along y and z, multiply by
-//           theta / (theta + lambda K^n) / V, inverse FFTs (for the packed
-//           plane the two real spectra are separated through their
-//           Hermitian symmetry);
+//           theta / (theta + lambda K^n) / (ny nz), inverse FFTs;
 //   pass C  per x-line: inverse x FFT, then the pointwise data step and the
 //           next state (or the composition of the warping's velocity).
+// Inside the iteration loop pass C and the next pass A run as one kernel
+// (mode kIterFwd): the new state is extrapolated and transformed along x on
+// the same lines without leaving the chip.
 #include <float.h>
 
 #include <type_traits>
@@ -85,36 +86,15 @@ int plane_threads(const Geo& g) {
   return t;
 }
 
-// Fewest Stockham stages for n, radices from {16, 12, 8, 6, 4, 3, 2}; among
-// plans with equally few stages the one with the largest leading radices.
-static bool plan_search(int m, int depth, int* out) {
-  static const int radices[7] = {16, 12, 8, 6, 4, 3, 2};
-  if (m == 1) return depth == 0;
-  if (depth == 0) return false;
-  for (int i = 0; i < 7; ++i) {
-    if (m % radices[i] == 0 && plan_search(m / radices[i], depth - 1, out + 1)) {
-      out[0] = radices[i];
-      return true;
-    }
-  }
-  return false;
-}
-
 FftPlan make_plan(int n) {
   FftPlan p{};
   p.n = n;
-  p.nstages = -1;
-  int rad[8] = {0};
-  for (int depth = 1; depth <= 8; ++depth) {
-    if (plan_search(n, depth, rad)) {
-      p.nstages = depth;
-      break;
-    }
-  }
+  const StockhamRadices rad = stockham_radices_ce(n);
+  p.nstages = rad.nstages;
   int ns = 1;
   for (int i = 0; i < p.nstages; ++i) {
     FftStage& s = p.st[i];
-    s.R = rad[i];
+    s.R = rad.R[i];
     s.Ns = ns;
     s.nb = n / s.R;
     s.twstride = n / (ns * s.R);
@@ -477,17 +457,65 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// pass A: t -> packed x half spectrum
-// X layout: X[((c * nx/2 + p) * nz + z) * ny + y], p < nx/2; p = 0 holds
-// (DC, Nyquist) of the real row as one complex value.
+// pass A: t -> x half spectrum
+// X layout: X[((c * (nx/2 + 1) + p) * nz + z) * ny + y], p <= nx/2.
 // ---------------------------------------------------------------------------
+// x-line transform of a block: the compile-time plan when NX is one of the
+// specialised lengths, else the host-made plan.
+template <int NX, bool INV>
+__device__ __forceinline__ void x_transform(float2* buf, const float2* tw, const FftPlan& px,
+                                            const XDivs& xd, int ls) {
+  if constexpr (NX > 0 && XL_LINE_FAST == 0)
+    fft_lines_ct<NX, kEpt, INV, XL_PADSH>(buf, tw, (int)xd.lines.d, ls);
+  else
+    fft_lines<kEpt, INV, XL_LINE_FAST, XL_PADSH>(buf, tw, px, xd.lines, 1, ls);
+}
+
+// Split the transformed line pairs of one block into the two rows' half
+// spectra, scaled by 1 / nx, and store them (row pairs contiguous along y).
+// Bins 0 and nx/2 of a real row are real: they go to planes 0 and nx/2 with
+// zero imaginary part.  With the 1 / nx here an x transform followed by the
+// inverse of pass C is the identity.
+template <int NX>
+__device__ __forceinline__ void store_half_spectrum(const Geo& g, const XDivs& xd, int ls,
+                                                    const float2* buf, float2* __restrict__ X,
+                                                    int y0, int z) {
+  const int nx = NX ? NX : g.nx, nh = nx / 2;
+  const int yb2 = (int)xd.yb2.d;
+  const int nthr = blockDim.x;
+  const int nout = 3 * nh * yb2;
+  const float s1 = 1.0f / (float)nx, sh = 0.5f * s1;
+  for (int idx = threadIdx.x; idx < nout; idx += nthr) {
+    const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
+    const int yp = idx - ck * yb2;
+    const int c = (int)fdiv((uint32_t)ck, xd.nh);
+    const int k = ck - c * nh;
+    const float2* Z = buf + (c * yb2 + yp) * ls;
+    float4 o;
+    if (k == 0) {
+      const float2 z0 = Z[0], zn = Z[lpad<XL_PADSH>(nh)];
+      o = make_float4(z0.x * s1, 0.f, z0.y * s1, 0.f);
+      float2* dn = X + ((size_t)(c * (nh + 1) + nh) * g.nz + z) * g.ny + y0 + 2 * yp;
+      *reinterpret_cast<float4*>(dn) = make_float4(zn.x * s1, 0.f, zn.y * s1, 0.f);
+    } else {
+      const float2 zk = Z[lpad<XL_PADSH>(k)], zm = Z[lpad<XL_PADSH>(nx - k)];
+      // a = (Zk + conj(Zm)) / 2 ; b = -i (Zk - conj(Zm)) / 2
+      o = make_float4(sh * (zk.x + zm.x), sh * (zk.y - zm.y), sh * (zk.y + zm.y),
+                      -sh * (zk.x - zm.x));
+    }
+    float2* dst = X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y0 + 2 * yp;
+    *reinterpret_cast<float4*>(dst) = o;
+  }
+}
+
+template <int NX>
 __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx,
                                                 const float* __restrict__ s1,
                                                 const float* __restrict__ s2, float gamma,
                                                 float2* __restrict__ X) {
   extern __shared__ float2 lds[];
-  const int nx = g.nx, nh = g.nx / 2, q4 = g.nx / 4;
+  const int nx = NX ? NX : g.nx, q4 = nx / 4;
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   float2* tw = lds;
   float2* buf = lds + nx;
@@ -536,32 +564,8 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
     }
   }
   __syncthreads();
-  fft_lines<kEpt, false, XL_LINE_FAST, XL_PADSH>(buf, tw, px, xd.lines, 1, ls);
-
-  // split into the two rows' half spectra and store (row pairs contiguous)
-  const int nout = 3 * nh * yb2;
-  for (int idx = threadIdx.x; idx < nout; idx += nthr) {
-    const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
-    const int yp = idx - ck * yb2;
-    const int c = (int)fdiv((uint32_t)ck, xd.nh);
-    const int k = ck - c * nh;
-    const float2* Z = buf + (c * yb2 + yp) * ls;
-    float4 o;
-    if (k == 0) {
-      // DC and Nyquist bins of the two rows are real: planes 0 and nh
-      const float2 z0 = Z[0], zn = Z[lpad<XL_PADSH>(nh)];
-      o = make_float4(z0.x, 0.f, z0.y, 0.f);
-      float2* dn = X + ((size_t)(c * (nh + 1) + nh) * g.nz + z) * g.ny + y0 + 2 * yp;
-      *reinterpret_cast<float4*>(dn) = make_float4(zn.x, 0.f, zn.y, 0.f);
-    } else {
-      const float2 zk = Z[lpad<XL_PADSH>(k)], zm = Z[lpad<XL_PADSH>(nx - k)];
-      // a = (Zk + conj(Zm)) / 2 ; b = -i (Zk - conj(Zm)) / 2
-      o = make_float4(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y), 0.5f * (zk.y + zm.y),
-                      -0.5f * (zk.x - zm.x));
-    }
-    float2* dst = X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y0 + 2 * yp;
-    *reinterpret_cast<float4*>(dst) = o;
-  }
+  x_transform<NX, false>(buf, tw, px, xd, ls);
+  store_half_spectrum<NX>(g, xd, ls, buf, X, y0, z);
 }
 
 static size_t pass_a_lds(const Geo& g) {
@@ -572,21 +576,27 @@ static size_t pass_a_lds(const Geo& g) {
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
                          const float* s2, float gamma, float2* X, hipStream_t st) {
   const int yb = xline_rows(g.ny);
-  hipLaunchKernelGGL(k_pass_a, dim3(g.ny / yb, g.nz), dim3(xline_threads(g)), pass_a_lds(g), st,
-                     g, px, make_xdivs(g), xline_stride(g.nx), t.twx, s1, s2, gamma, X);
+  const dim3 grid(g.ny / yb, g.nz), block(xline_threads(g));
+  const size_t lds = pass_a_lds(g);
+  const XDivs xd = make_xdivs(g);
+  const int ls = xline_stride(g.nx);
+#define NADMM_PASS_A(N) \
+  hipLaunchKernelGGL(k_pass_a<N>, grid, block, lds, st, g, px, xd, ls, t.twx, s1, s2, gamma, X)
+  switch (g.nx) {
+    case 32: NADMM_PASS_A(32); break;
+    case 64: NADMM_PASS_A(64); break;
+    case 96: NADMM_PASS_A(96); break;
+    case 128: NADMM_PASS_A(128); break;
+    case 192: NADMM_PASS_A(192); break;
+    default: NADMM_PASS_A(0); break;
+  }
+#undef NADMM_PASS_A
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // pass B: y-z plane FFT, spectral multiply, inverse
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float spectral_mult(float k0, float lambda, float theta, int order,
-                                               float inv_v) {
-  float kn = k0;
-  for (int i = 1; i < order; ++i) kn *= k0;
-  return theta * inv_v * __builtin_amdgcn_rcpf(theta + lambda * kn);
-}
-
 // Stage schedules of pass B.  PlansRT reads the (host-made) plans from LDS
 // and dispatches every stage's radix at run time; PlansCT<NY, NZ> has the
 // same plans as compile-time constants, so only the radices a size uses are
@@ -670,7 +680,8 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   const int p = blockIdx.x, c = blockIdx.y;
   float2* plane = X + (size_t)(c * np + p) * nz * ny;
   const float4* plane4 = reinterpret_cast<const float4*>(plane);
-  const float inv_v = 1.0f / (float)g.V;
+  // the x transform of pass A already carries 1 / nx of the inverse's 1 / V
+  const float inv_v = 1.0f / (float)(ny * nz);
   const int nlw_y = 64 / (NY ? PlansCT<NY ? NY : 32, NZ ? NZ : 32>::PY.L : py0.L);
 
   // Rows of the y transform are owned by wavefronts: lines [l0, l0 + nlw_y)
@@ -837,11 +848,11 @@ __device__ __forceinline__ void f4set(float4& v, int e, float s) {
   if (e == 0) v.x = s; else if (e == 1) v.y = s; else if (e == 2) v.z = s; else v.w = s;
 }
 
-template <int MODE>
+template <int MODE, int NX>
 __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx, PassCArgs a) {
   extern __shared__ float2 lds[];
-  const int nx = g.nx, nh = g.nx / 2, q4 = g.nx / 4;
+  const int nx = NX ? NX : g.nx, nh = nx / 2, q4 = nx / 4;
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   const int nthr = blockDim.x;
   float2* tw = lds;
@@ -864,6 +875,16 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
       if (k == 0)  // the Nyquist plane
         inn[it] = *reinterpret_cast<const float4*>(src + (size_t)nh * g.nz * g.ny);
     }
+  }
+  // float4 runs of 4 voxels along x for the pointwise part
+  const int nitems = yb * q4;
+  constexpr int MI = 2;  // runs per thread (host checks yb * nx / 4 <= 2 * threads)
+  int gi[MI];
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = threadIdx.x + it * nthr;
+    const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
+    gi[it] = (z * g.ny + y0 + yy) * nx + 4 * x4;
   }
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
 #pragma unroll
@@ -888,25 +909,25 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
     }
   }
   __syncthreads();
-  fft_lines<kEpt, true, XL_LINE_FAST, XL_PADSH>(buf, tw, px, xd.lines, 1, ls);
+  x_transform<NX, true>(buf, tw, px, xd, ls);
 
-  const float* bf = reinterpret_cast<const float*>(buf);
-  const int nitems = yb * q4;  // float4 runs of 4 voxels along x
-  constexpr int MI = 2;        // runs per thread (host checks yb * nx / 4 <= 2 * threads)
-  float4 yv[MI][3];
-  int gi[MI];
-#pragma unroll
-  for (int it = 0; it < MI; ++it) {
+  float* bf = reinterpret_cast<float*>(buf);
+  // LDS slots of run it, component c: four consecutive x of one real row
+  auto run_slot = [&](int it, int c) {
     const int idx = threadIdx.x + it * nthr;
-    if (idx < nitems) {
-      const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
-      gi[it] = (z * g.ny + y0 + yy) * nx + 4 * x4;
+    const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
+    return bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<XL_PADSH>(4 * x4)) + (yy & 1);
+  };
+  float4 yv[MI][3];
+  if (MODE != kIterFwd) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float* rowp = bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<XL_PADSH>(4 * x4)) + (yy & 1);
-        yv[it][c] = make_float4(rowp[0], rowp[2], rowp[4], rowp[6]);
-      }
-    }
+    for (int it = 0; it < MI; ++it)
+      if (threadIdx.x + it * nthr < nitems)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float* rowp = run_slot(it, c);
+          yv[it][c] = make_float4(rowp[0], rowp[2], rowp[4], rowp[6]);
+        }
   }
 
   if (MODE == kOutY) {
@@ -915,51 +936,66 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
       if (threadIdx.x + it * nthr < nitems)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
-  } else if (MODE == kIter) {
-    // all global loads of every run first (out may alias s2)
-    float4 s1v[MI][3], s2v[MI][3], jv[MI][3], rv[MI];
-#pragma unroll
+  } else if (MODE == kIterFwd) {
+    // one run at a time keeps the register footprint small (occupancy hides
+    // the latency); out may alias s2, and each run is read and written by
+    // the same thread only
+#pragma unroll 1
     for (int it = 0; it < MI; ++it) {
-      if (threadIdx.x + it * nthr < nitems) {
+      const int idx = threadIdx.x + it * nthr;
+      if (idx >= nitems) break;
+      const int yy = (int)fdiv((uint32_t)idx, xd.q4);
+      const int go = (z * g.ny + y0 + yy) * nx + 4 * (idx - yy * q4);
+      float4 s1v[3], s2v[3], jv[3], yr[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s1v[c] = ld4(a.s1 + c * g.V + go);
+        s2v[c] = a.s2 ? ld4(a.s2 + c * g.V + go) : s1v[c];
+        jv[c] = ld4(a.J + c * g.V + go);
+      }
+      const float4 rv = ld4(a.r + go);
+      float* slot[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        slot[c] = run_slot(it, c);
+        yr[c] = make_float4(slot[c][0], slot[c][2], slot[c][4], slot[c][6]);
+      }
+      float4 so[3], vo[3];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float t[3], av[3], j[3], v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          s1v[it][c] = ld4(a.s1 + c * g.V + gi[it]);
-          if (a.s2) s2v[it][c] = ld4(a.s2 + c * g.V + gi[it]);
-          jv[it][c] = ld4(a.J + c * g.V + gi[it]);
+          const float s = f4get(s1v[c], e);
+          t[c] = fmaf(a.gamma, s - f4get(s2v[c], e), s);
+          av[c] = 2.0f * f4get(yr[c], e) - t[c];
+          j[c] = f4get(jv[c], e);
         }
-        rv[it] = ld4(a.r + gi[it]);
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < MI; ++it) {
-      if (threadIdx.x + it * nthr < nitems) {
-        float4 so[3], vo[3];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          float t[3], av[3], j[3], v[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            float s = f4get(s1v[it][c], e);
-            if (a.s2) s = fmaf(a.gamma, s - f4get(s2v[it][c], e), s);
-            t[c] = s;
-            av[c] = 2.0f * f4get(yv[it][c], e) - s;
-            j[c] = f4get(jv[it][c], e);
-          }
-          data_step(av, j, f4get(rv[it], e), a.theta, a.eps, a.data_term, v);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            // s^k = v + b_hat = v + t - y
-            f4set(so[c], e, v[c] + (t[c] - f4get(yv[it][c], e)));
-            f4set(vo[c], e, v[c]);
-          }
-        }
+        data_step(av, j, f4get(rv, e), a.theta, a.eps, a.data_term, v);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          st4(a.out + c * g.V + gi[it], so[c]);
-          if (a.v_out) st4(a.v_out + c * g.V + gi[it], vo[c]);
+          // s^k = v + b_hat = v + t - y
+          f4set(so[c], e, v[c] + (t[c] - f4get(yr[c], e)));
+          f4set(vo[c], e, v[c]);
         }
       }
+      const float gn = a.gamma_next;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        st4(a.out + c * g.V + go, so[c]);
+        if (a.v_out) st4(a.v_out + c * g.V + go, vo[c]);
+        // next solve's input t' = s^k + gamma_next (s^k - s^{k-1}), written
+        // over the slots this thread read y from
+        const float4 n = so[c], o = s1v[c];
+        slot[c][0] = fmaf(gn, n.x - o.x, n.x);
+        slot[c][2] = fmaf(gn, n.y - o.y, n.y);
+        slot[c][4] = fmaf(gn, n.z - o.z, n.z);
+        slot[c][6] = fmaf(gn, n.w - o.w, n.w);
+      }
     }
+    __syncthreads();
+    x_transform<NX, false>(buf, tw, px, xd, ls);
+    store_half_spectrum<NX>(g, xd, ls, buf, a.X, y0, z);
   } else if (MODE == kFinalWB) {
 #pragma unroll
     for (int it = 0; it < MI; ++it) {
@@ -1016,12 +1052,25 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
   const size_t lds = pass_a_lds(g);
   const XDivs xd = make_xdivs(g);
   const int ls = xline_stride(g.nx);
-  switch (mode) {
-    case kOutY: hipLaunchKernelGGL(k_pass_c<kOutY>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
-    case kIter: hipLaunchKernelGGL(k_pass_c<kIter>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
-    case kFinalWB: hipLaunchKernelGGL(k_pass_c<kFinalWB>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
-    default: hipLaunchKernelGGL(k_pass_c<kCompose>, grid, block, lds, st, g, px, xd, ls, t.twx, a); break;
+#define NADMM_PASS_C(M, N) \
+  hipLaunchKernelGGL((k_pass_c<M, N>), grid, block, lds, st, g, px, xd, ls, t.twx, a)
+#define NADMM_PASS_C_NX(M)                 \
+  switch (g.nx) {                          \
+    case 32: NADMM_PASS_C(M, 32); break;   \
+    case 64: NADMM_PASS_C(M, 64); break;   \
+    case 96: NADMM_PASS_C(M, 96); break;   \
+    case 128: NADMM_PASS_C(M, 128); break; \
+    case 192: NADMM_PASS_C(M, 192); break; \
+    default: NADMM_PASS_C(M, 0); break;    \
   }
+  switch (mode) {
+    case kOutY: NADMM_PASS_C_NX(kOutY); break;
+    case kIterFwd: NADMM_PASS_C_NX(kIterFwd); break;
+    case kFinalWB: NADMM_PASS_C_NX(kFinalWB); break;
+    default: NADMM_PASS_C_NX(kCompose); break;
+  }
+#undef NADMM_PASS_C_NX
+#undef NADMM_PASS_C
   return hipGetLastError();
 }
 
