@@ -43,6 +43,11 @@ static_assert(XL_PADSH == 0 || XL_PADSH >= 2, "float4 runs must not straddle a p
 #ifndef XL_EXTRA
 #define XL_EXTRA 0
 #endif
+// Rows of one z-slice per workgroup of the x-line passes (largest even
+// divisor of ny up to this).
+#ifndef XL_MAX_ROWS
+#define XL_MAX_ROWS 8
+#endif
 
 namespace nadmm {
 
@@ -54,7 +59,7 @@ static inline int xline_stride(int nx) { return xl_pad_host(nx) + XL_EXTRA; }
 // host-side geometry helpers
 // ---------------------------------------------------------------------------
 int xline_rows(int ny) {
-  for (int yb = 16; yb >= 2; yb -= 2)
+  for (int yb = XL_MAX_ROWS; yb >= 2; yb -= 2)
     if (ny % yb == 0) return yb;
   return 2;
 }
@@ -460,6 +465,22 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st) {
 // pass A: t -> x half spectrum
 // X layout: X[((c * (nx/2 + 1) + p) * nz + z) * ny + y], p <= nx/2.
 // ---------------------------------------------------------------------------
+// Tile (y-block, z) of an x-line workgroup.  Workgroups are dispatched
+// round-robin over the 8 XCDs, each with its own L2; when the grid allows,
+// each XCD gets one contiguous range of tiles instead, so that neighbouring
+// tiles (which share 128-byte lines of the half spectrum, and z-planes for
+// the gathers) meet in the same L2.  (XCD_REMAP 0 keeps the hardware order.)
+#ifndef XCD_REMAP
+#define XCD_REMAP 1
+#endif
+__device__ __forceinline__ void xline_tile(int& by, int& z) {
+  const int nby = gridDim.x, n = gridDim.x * gridDim.y;
+  int l = blockIdx.x + nby * blockIdx.y;
+  if (XCD_REMAP && (n & 7) == 0) l = (l & 7) * (n >> 3) + (l >> 3);
+  z = l / nby;
+  by = l - z * nby;
+}
+
 // x-line transform of a block: the compile-time plan when NX is one of the
 // specialised lengths, else the host-made plan.
 template <int NX, bool INV>
@@ -519,7 +540,9 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   float2* tw = lds;
   float2* buf = lds + nx;
-  const int y0 = blockIdx.x * yb, z = blockIdx.y;
+  int by, z;
+  xline_tile(by, z);
+  const int y0 = by * yb;
   const int nthr = blockDim.x;
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
 
@@ -857,7 +880,9 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
   const int nthr = blockDim.x;
   float2* tw = lds;
   float2* buf = lds + nx;
-  const int y0 = blockIdx.x * yb, z = blockIdx.y;
+  int by, z;
+  xline_tile(by, z);
+  const int y0 = by * yb;
 
   // unpack two rows' half spectra into one complex row: Z = Xa + i Xb
   const int nin = 3 * nh * yb2;
