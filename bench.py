@@ -7,10 +7,20 @@ iterations, n = 2, lambda = 0.01, theta = 0.1, with inputs already resident
 in GPU memory.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+HBM traffic of the dominant kernel comes from two rocprofv3 --pmc runs of
+this script (FETCH_SIZE, then WRITE_SIZE) with --copy-probe, which first runs
+a device-to-device copy of known size whose counter readings calibrate the
+scale; `--traffic-from FETCH_CSV WRITE_CSV` turns the two counter files into
+the record kept under profiles/.  The record names the digest of the kernel
+sources it was taken on, and the bench line reports it only while the
+sources still have that digest.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -20,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+KERNEL_SOURCES = ["kernels.hip", "kernels.h", "fft_lds.h"]
+# rocprofv3 kernel-name prefixes of the replayable kernels
+KERNEL_NAMES = {"pass_a_fwd_x": "nadmm::k_pass_a<", "pass_b_yz_solve": "nadmm::k_pass_b<",
+                "pass_ca_iter": "nadmm::k_pass_c<1,"}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 # Algorithmic bytes per voxel of each kernel kind (inputs read once, outputs
 # written once; float32 fields, packed half spectrum = 4 B per component).
@@ -42,7 +57,72 @@ def parse():
     ap.add_argument("--workload", default="phantom128x128x96")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the bfloat16-image run at 192x192x128 (vs the float32 path)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a device-to-device copy of known size first (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the traffic record from two rocprofv3 --pmc counter files and exit")
     return ap.parse_args()
+
+
+def sources_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2109_12688_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def copy_probe_bytes(V: int) -> int:
+    return 3 * V * 4  # one vector field, read once and written once
+
+
+def traffic_record(fetch_csv, write_csv, workload, kernel):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of `kernel`, each scaled by
+    what the same counter reads for the copy probe of known size."""
+    def per_dispatch(path, counter):
+        sums = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].replace("void ", "")
+            key = next((k for k, pre in list(KERNEL_NAMES.items()) + [("copy", COPY_KERNEL)]
+                        if name.startswith(pre)), None)
+            if key is None:
+                continue
+            d = sums.setdefault(key, {})
+            d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        return {k: sum(v.values()) / len(v) for k, v in sums.items()}
+
+    import numpy as np
+    import synth
+    V = int(np.prod(synth.WORKLOADS[workload]["dims"]))
+    cb = copy_probe_bytes(V)
+    f, w = per_dispatch(fetch_csv, "FETCH_SIZE"), per_dispatch(write_csv, "WRITE_SIZE")
+    sf, sw = cb / (1024.0 * f["copy"]), cb / (1024.0 * w["copy"])
+    rec = {"kernel": kernel, "workload": workload, "sources_sha256": sources_digest(),
+           "fetch_kib_per_dispatch": round(f[kernel], 1), "write_kib_per_dispatch": round(w[kernel], 1),
+           "copy_bytes": cb, "copy_fetch_kib": round(f["copy"], 1), "copy_write_kib": round(w["copy"], 1),
+           "fetch_scale": round(sf, 4), "write_scale": round(sw, 4)}
+    rec["read_bytes_per_launch"] = round(1024.0 * f[kernel] * sf)
+    rec["write_bytes_per_launch"] = round(1024.0 * w[kernel] * sw)
+    rec["traffic_bytes_per_launch"] = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return rec
+
+
+def stored_traffic(workload, kernel):
+    """HBM bytes per launch from the committed counter record, or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("record: "):
+            rec = json.loads(line[len("record: "):])
+            if rec.get("sources_sha256") == sources_digest() and rec.get("kernel") == kernel:
+                return rec
+    return None
 
 
 def log(msg):
@@ -72,8 +152,54 @@ def cpu_baseline(pair, w):
                       f"numpy float64 single thread, {dt:.2f} s"}
 
 
+def bf16_vs_plain(api, torch, synth, reps=3):
+    """The precision workload (192x192x128 phantom, n = 3, lambda = 0.005,
+    10 x 30) registered from bfloat16 and from float32 images on the same
+    GPU; ms per registration of each (event-timed, inputs resident)."""
+    name = "phantom192x192x128"
+    w = synth.WORKLOADS[name]
+    log(f"generating {name}")
+    pair = synth.make_pair(name)
+    shp = pair.fixed.shape
+    ws = api.workspace(shp)
+    f32 = (torch.from_numpy(pair.fixed).cuda(), torch.from_numpy(pair.moving).cuda())
+    b16 = tuple(t.to(torch.bfloat16) for t in f32)
+    out = {"disp": torch.empty((3,) + shp, device="cuda"), "warped": torch.empty(shp, device="cuda")}
+    stream = torch.cuda.current_stream()
+
+    def ms(imgs):
+        def run():
+            api.register(imgs[0], imgs[1], w["lam"], w["theta"], w["order"], w["outer"], w["iters"],
+                         ws=ws, out=out)
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    plain, bf = ms(f32), ms(b16)
+    stats, nneg, _ = api.jacobian(out["disp"], ws=ws)
+    torch.cuda.synchronize()
+    log(f"{name}: float32 images {plain:.3f} ms, bfloat16 images {bf:.3f} ms per registration")
+    return {"workload": name, "dims_xyz": list(w["dims"]), "outer": w["outer"], "iters": w["iters"],
+            "order": w["order"], "lambda": w["lam"], "steps": reps,
+            "ms_per_registration_fp32_images": round(plain, 3),
+            "ms_per_registration_bf16_images": round(bf, 3),
+            "registrations_per_s_bf16": round(1000.0 / bf, 3),
+            "bf16_vs_plain": round(plain / bf, 4),
+            "min_det_J_bf16": float(stats[0].item()), "n_det_nonpos_bf16": int(nneg.item())}
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        print("record: " + json.dumps(traffic_record(args.traffic_from[0], args.traffic_from[1],
+                                                       args.workload, "pass_ca_iter")))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
               "part of this build", file=sys.stderr)
@@ -102,22 +228,39 @@ def main():
         return api.register(fixed, moving, w["lam"], w["theta"], w["order"], w["outer"], w["iters"],
                             ws=ws, out=out)
 
+    stream = torch.cuda.current_stream()
+    # achievable copy bandwidth (device-to-device copy of one vector field)
+    src = torch.rand((3,) + shp, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3 if args.copy_probe else 1):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ncopy = 50
+    c0.record(stream)
+    for _ in range(ncopy):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * copy_probe_bytes(V) / (c0.elapsed_time(c1) / ncopy * 1e-3) / 1e9
+    del src, dst
+
     log("warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     log(f"timing {args.steps} registrations")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for i in range(args.steps):
         step()
-    e1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
+    ms_per_step = ev[0].elapsed_time(ev[-1]) / args.steps
+    per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     log(f"{ms_per_step:.3f} ms/registration (wall {1e3 * wall / args.steps:.3f})")
 
     # per-kernel durations from HIP events bracketing each library launch
@@ -142,11 +285,15 @@ def main():
     bpv = BYTES_PER_VOXEL[dom]
     avg_s = avg_ms / 1e3
     achieved = bpv * V / avg_s / 1e9
+    trec = stored_traffic(args.workload, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "bytes_per_launch": bpv * V, "avg_us": round(avg_s * 1e6, 3),
                 "avg_us_event_bracketed": round(1e3 * prof[dom][1] / prof[dom][0], 3),
-                "traffic": None}
+                "traffic": trec["traffic_bytes_per_launch"] if trec else None,
+                "traffic_read_write": ([trec["read_bytes_per_launch"], trec["write_bytes_per_launch"]]
+                                       if trec else None),
+                "copy_gbs": round(copy_gbs, 1)}
 
     stats, nneg, _ = api.jacobian(out["disp"], ws=ws)
     torch.cuda.synchronize()
@@ -158,6 +305,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_p10_p50_p90": [round(float(np.percentile(per_step, q)), 4) for q in (10, 50, 90)],
         "ms_per_admm_iter": round(per_iter_us / 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
@@ -172,6 +320,8 @@ def main():
         "min_det_J": float(stats[0].item()),
         "n_det_nonpos": int(nneg.item()),
     }
+    if not args.no_bf16:
+        res["bf16"] = bf16_vs_plain(api, torch, synth)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the CPU")
         res["cpu_baseline"] = cpu_baseline(pair, w)

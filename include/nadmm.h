@@ -26,9 +26,10 @@
  *           HIP runtime failures return NADMM_ERR_HIP.  nadmm_last_error()
  *           gives a per-thread message for the last non-OK status.
  * Sizes.    nx must be a multiple of 4 and ny even; every dimension must be 2^a * 3^b with
- *           4 <= n <= 256, and ny*nz <= 16384 (the y-z spectral plane must
- *           fit one compute unit's local memory).  Other sizes return
- *           NADMM_ERR_UNSUPPORTED_SIZE.
+ *           4 <= n <= 256.  Other sizes return NADMM_ERR_UNSUPPORTED_SIZE.
+ *           (y-z spectral planes of up to 16384 points are transformed in
+ *           one pass in a compute unit's local memory, larger ones in three
+ *           passes; results do not depend on which.)
  */
 #ifndef NADMM_H
 #define NADMM_H
@@ -110,6 +111,35 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p,
                             const float* init_disp, float* disp, float* warped,
                             float* velocities, void* workspace, size_t workspace_bytes,
                             void* stream);
+
+/* nadmm_register with the two images stored as bfloat16 (each element the
+ * upper 16 bits of an IEEE float32, round-to-nearest-even from the float32
+ * image being the caller's job).  Image values are widened exactly to
+ * float32 where they are read (the warps of the moving image and the
+ * residual against the fixed image); the warped image, its gradient, every
+ * field and every transform stay float32.  Arguments, layout, workspace and
+ * errors as for nadmm_register; `warped` is float32. */
+nadmm_status nadmm_register_bf16(nadmm_dims d, const nadmm_params* p,
+                                 const uint16_t* fixed, const uint16_t* moving,
+                                 const float* init_disp, float* disp, float* warped,
+                                 float* velocities, void* workspace, size_t workspace_bytes,
+                                 void* stream);
+
+/* Batched registration: `batch` (1..4096) independent pairs of one size
+ * and one parameter set, stored back to back in every buffer (pair i's
+ * fixed image at fixed + i*V, its displacement at disp + i*3V, ...; init_disp
+ * and warped likewise, both may be NULL).  Each launch of the path covers
+ * all pairs (the pair is the last grid index), so small volumes fill the
+ * GPU and the launch count does not grow with the batch.  Results are those
+ * of `batch` separate nadmm_register calls, bit for bit.  The workspace is
+ * nadmm_workspace_size_batch bytes; no per-warping velocities.  Errors as
+ * for nadmm_register, plus NADMM_ERR_INVALID_ARG for batch out of range.
+ * (Pairs of several sizes: one call per size, e.g. on separate streams.) */
+nadmm_status nadmm_workspace_size_batch(nadmm_dims d, int32_t batch, size_t* bytes);
+nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_params* p,
+                                  const float* fixed, const float* moving,
+                                  const float* init_disp, float* disp, float* warped,
+                                  void* workspace, size_t workspace_bytes, void* stream);
 
 /* One ADMM solve (Eq. (5), (6)) for a given linearised data term:
  * `p->iters` iterations from zero with J = grad I1^w (vector field) and

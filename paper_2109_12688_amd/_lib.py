@@ -42,6 +42,11 @@ _SIGS = {
     "nadmm_workspace_size": ([Dims, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "nadmm_register": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                        ctypes.c_int),
+    "nadmm_register_bf16": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                             _P], ctypes.c_int),
+    "nadmm_workspace_size_batch": ([Dims, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "nadmm_register_batch": ([Dims, ctypes.c_int32, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P,
+                              ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_admm": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_fourier_solve": ([Dims, ctypes.POINTER(Params), _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_warp": ([Dims, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),

@@ -71,10 +71,14 @@ def register(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float
              ws: torch.Tensor | None = None, out: dict | None = None) -> dict:
     """Full registration (Sec. 2 scheme with Sec. 3 ADMM).  Returns a dict with
     'disp' (3, nz, ny, nx), 'warped' (nz, ny, nx) and optionally 'velocities'
-    (outer, 3, nz, ny, nx).  ``out`` may supply preallocated output tensors."""
-    _check(fixed, "fixed")
+    (outer, 3, nz, ny, nx).  ``out`` may supply preallocated output tensors.
+    ``fixed`` and ``moving`` are both float32, or both bfloat16 (stored images
+    widened to float32 where read; every output is float32)."""
+    bf16 = fixed.dtype == torch.bfloat16
+    img_dtype = torch.bfloat16 if bf16 else torch.float32
+    _check(fixed, "fixed", dtype=img_dtype)
     shp = tuple(fixed.shape)
-    _check(moving, "moving", shp)
+    _check(moving, "moving", shp, dtype=img_dtype)
     vshp = (3,) + shp
     if init_disp is not None:
         _check(init_disp, "init_disp", vshp)
@@ -91,13 +95,53 @@ def register(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float
         vels = torch.empty((outer,) + vshp, dtype=torch.float32, device=dev)
     ws = _ws(shp, ws, dev)
     p = params(lam, theta, order, outer, iters, data_term, eps)
-    _lib.call("nadmm_register", dims_of(shp), ctypes.byref(p), _ptr(fixed), _ptr(moving),
+    _lib.call("nadmm_register_bf16" if bf16 else "nadmm_register", dims_of(shp), ctypes.byref(p),
+              _ptr(fixed), _ptr(moving),
               _ptr(init_disp), _ptr(disp), _ptr(warped), _ptr(vels) if return_velocities else None,
               _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
     res = {"disp": disp, "warped": warped}
     if return_velocities:
         res["velocities"] = vels
     return res
+
+
+def workspace_batch(vol_shape, batch: int, device="cuda") -> torch.Tensor:
+    n = ctypes.c_size_t(0)
+    _lib.call("nadmm_workspace_size_batch", dims_of(vol_shape), ctypes.c_int32(batch), ctypes.byref(n))
+    return torch.empty(int(n.value), dtype=torch.uint8, device=device)
+
+
+def register_batch(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
+                   outer: int, iters: int, data_term: int = 2, eps: float = 1e-8,
+                   init_disp: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                   out: dict | None = None) -> dict:
+    """``batch`` pairs of one size in one call: fixed, moving (batch, nz, ny, nx)
+    float32; returns 'disp' (batch, 3, nz, ny, nx) and 'warped' (batch, nz,
+    ny, nx).  Bit-identical to registering the pairs one by one."""
+    _check(fixed, "fixed")
+    shp = tuple(fixed.shape)
+    if len(shp) != 4:
+        raise ValueError("fixed must have shape (batch, nz, ny, nx)")
+    _check(moving, "moving", shp)
+    b, vol = shp[0], shp[1:]
+    vshp = (b, 3) + vol
+    if init_disp is not None:
+        _check(init_disp, "init_disp", vshp)
+    out = dict(out or {})
+    disp = out.get("disp")
+    if disp is None:
+        disp = torch.empty(vshp, dtype=torch.float32, device=fixed.device)
+    warped = out.get("warped")
+    if warped is None:
+        warped = torch.empty(shp, dtype=torch.float32, device=fixed.device)
+    if ws is None:
+        ws = workspace_batch(vol, b, fixed.device)
+    _check(ws, "workspace", dtype=torch.uint8)
+    p = params(lam, theta, order, outer, iters, data_term, eps)
+    _lib.call("nadmm_register_batch", dims_of(vol), ctypes.c_int32(b), ctypes.byref(p), _ptr(fixed),
+              _ptr(moving), _ptr(init_disp), _ptr(disp), _ptr(warped), _ptr(ws),
+              ctypes.c_size_t(ws.numel()), _stream())
+    return {"disp": disp, "warped": warped}
 
 
 def admm(J: torch.Tensor, r: torch.Tensor, lam: float, theta: float, order: int, iters: int,

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "../../include/nadmm.h"
@@ -90,9 +91,6 @@ nadmm_status check_dims(const nadmm_dims& d) {
   if (d.nx % 4 || d.ny % 2)
     return fail(NADMM_ERR_UNSUPPORTED_SIZE,
                 "dims (%d, %d, %d): nx must be a multiple of 4 and ny even", d.nx, d.ny, d.nz);
-  if (d.ny * d.nz > 16384)
-    return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d): ny*nz must be <= 16384", d.nx,
-                d.ny, d.nz);
   if (!launch_shape_ok(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}))
     return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d): no valid launch shape", d.nx,
                 d.ny, d.nz);
@@ -139,9 +137,11 @@ struct Layout {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-Layout layout(const nadmm_dims& d) {
-  const size_t V = (size_t)d.nx * d.ny * d.nz;
-  const size_t f3 = align256(3 * V * sizeof(float)), f1 = align256(V * sizeof(float));
+// Per-pair regions hold `batch` pairs back to back; tables and Jacobian
+// partials are shared.
+Layout layout(const nadmm_dims& d, int batch = 1) {
+  const size_t V = (size_t)d.nx * d.ny * d.nz, B = (size_t)batch;
+  const size_t f3 = align256(B * 3 * V * sizeof(float)), f1 = align256(B * V * sizeof(float));
   Layout L;
   size_t o = 0;
   L.J = o; o += f3;
@@ -149,7 +149,7 @@ Layout layout(const nadmm_dims& d) {
   L.iw = o; o += f1;
   L.s1 = o; o += f3;
   L.s2 = o; o += f3;
-  L.X = o; o += align256((size_t)3 * (d.nx / 2 + 1) * d.ny * d.nz * 2 * sizeof(float));
+  L.X = o; o += align256(B * 3 * (d.nx / 2 + 1) * d.ny * d.nz * 2 * sizeof(float));
   L.u = o; o += f3;
   L.jac = o; o += align256(kJacBlocks * 4 * sizeof(double));
   L.tab = o; o += align256(tables_bytes(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}));
@@ -157,12 +157,18 @@ Layout layout(const nadmm_dims& d) {
   return L;
 }
 
-nadmm_status check_ws(const nadmm_dims& d, void* ws, size_t bytes) {
+nadmm_status check_ws(const nadmm_dims& d, void* ws, size_t bytes, int batch = 1) {
   CHECK(check_ptr(ws, "workspace", false));
-  const size_t need = layout(d).total;
+  const size_t need = layout(d, batch).total;
   if (bytes < need)
     return fail(NADMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
                 bytes, need);
+  return NADMM_OK;
+}
+
+nadmm_status check_batch(int32_t batch) {
+  if (batch < 1 || batch > 4096)
+    return fail(NADMM_ERR_INVALID_ARG, "batch must be in [1, 4096] (got %d)", batch);
   return NADMM_OK;
 }
 
@@ -194,12 +200,14 @@ Plans plans(const nadmm_dims& d) { return Plans{make_plan(d.nx), make_plan(d.ny)
 // One application of the w-step operator S to t = s1 + gamma (s1 - s2)
 // through passes A and B; pass C (with its mode) is issued by the caller.
 hipError_t spectral_ab(const Geo& g, const Plans& pl, const Tables& tb, const nadmm_params* p,
-                       const float* s1, const float* s2, float gamma, float2* X, hipStream_t st) {
-  hipError_t e =
-      timed(KK_PASS_A, st, [&] { return launch_pass_a(g, pl.x, tb, s1, s2, gamma, X, st); });
+                       const float* s1, const float* s2, float gamma, float2* X, hipStream_t st,
+                       int batch = 1) {
+  hipError_t e = timed(KK_PASS_A, st, [&] {
+    return launch_pass_a(g, pl.x, tb, s1, s2, gamma, X, st, batch);
+  });
   if (e != hipSuccess) return e;
   return timed(KK_PASS_B, st, [&] {
-    return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
+    return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch);
   });
 }
 
@@ -210,9 +218,10 @@ hipError_t spectral_ab(const Geo& g, const Plans& pl, const Tables& tb, const na
 // warping's final pass C.
 nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
                              const nadmm_params* p, const float* J, const float* r, float*& cur,
-                             float*& prev, float2* X, float* v_last, hipStream_t st) {
+                             float*& prev, float2* X, float* v_last, hipStream_t st,
+                             int batch = 1) {
   const std::vector<double> gam = nesterov_gammas(p->iters);
-  HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st));  // gamma_0 = 0: t = s^0
+  HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st, batch));  // gamma_0 = 0: t = s^0
   for (int k = 1; k < p->iters; ++k) {
     PassCArgs a{};
     a.X = X;
@@ -227,13 +236,88 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     a.data_term = p->data_term;
     a.out = prev;  // s^k overwrites s^{k-2} voxel by voxel
     a.v_out = (k == p->iters - 1) ? v_last : nullptr;
-    HIP_TRY(timed(KK_PASS_CA_ITER, st, [&] { return launch_pass_c(g, pl.x, tb, kIterFwd, a, st); }));
+    HIP_TRY(timed(KK_PASS_CA_ITER, st, [&] {
+      return launch_pass_c(g, pl.x, tb, kIterFwd, a, st, batch);
+    }));
     HIP_TRY(timed(KK_PASS_B, st, [&] {
-      return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
+      return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch);
     }));
     float* tmp = cur;
     cur = prev;
     prev = tmp;
+  }
+  return NADMM_OK;
+}
+
+// The registration of nadmm_register / _bf16 / _batch; T is the image
+// element type (float, or uint16_t holding bfloat16 bit patterns); `batch`
+// pairs of one size, back to back in every buffer (velocities only for 1).
+template <typename T>
+nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, const T* moving,
+                           const float* init_disp, float* disp, float* warped, float* velocities,
+                           void* workspace, size_t workspace_bytes, void* stream, int batch) {
+  constexpr bool kBf16 = std::is_same<T, uint16_t>::value;
+  CHECK(check_dims(d));
+  CHECK(check_params(p, true));
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(init_disp, "init_disp", true));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(warped, "warped", true));
+  CHECK(check_ptr(velocities, "velocities", true));
+  CHECK(check_ws(d, workspace, workspace_bytes, batch));
+  const Geo g = geo(d);
+  const Plans pl = plans(d);
+  const Layout L = layout(d, batch);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t V = (size_t)g.V;
+  float* J = at<float>(workspace, L.J);
+  float* r = at<float>(workspace, L.r);
+  float* iw = at<float>(workspace, L.iw);
+  float* S1 = at<float>(workspace, L.s1);
+  float* S2 = at<float>(workspace, L.s2);
+  float2* X = at<float2>(workspace, L.X);
+  float* U = at<float>(workspace, L.u);
+  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
+  HIP_TRY(launch_tables(g, tb, st));
+
+  // Displacement buffers alternate between U and disp so that the last
+  // warping writes disp.
+  auto dst_of = [&](int c) { return ((p->outer - 1 - c) % 2 == 0) ? disp : U; };
+  const float* u_src;
+  if (init_disp) {
+    u_src = init_disp;
+  } else {
+    float* z = (p->outer > 0 && dst_of(0) == disp) ? U : disp;
+    HIP_TRY(timed(KK_FILL, st, [&] { return launch_fill(z, 0.0f, 3 * V * batch, st); }));
+    u_src = z;
+  }
+  if (p->outer == 0) {
+    if (u_src != disp) HIP_TRY(hipMemcpyAsync(disp, u_src, 3 * V * batch * sizeof(float),
+                                              hipMemcpyDeviceToDevice, st));
+    if (warped) HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, disp, warped, st, batch); }));
+    return NADMM_OK;
+  }
+  HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, u_src, iw, st, batch); }));
+  for (int c = 0; c < p->outer; ++c) {
+    const bool last = (c == p->outer - 1);
+    // linearised data term at the current warp, and s^0 (Eq. (6) from zero)
+    HIP_TRY(timed(KK_GRAD, st, [&] { return launch_grad_resid(g, iw, fixed, J, r, S1, (float)p->theta, (float)p->eps,
+                              p->data_term, st, batch); }));
+    float* cur = S1;
+    float* prev = S2;
+    CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, nullptr, st, batch));
+    // final w = S s^{K-1}, composed onto the displacement
+    PassCArgs a{};
+    a.X = X;
+    a.out = dst_of(c);
+    a.u_old = u_src;
+    if constexpr (kBf16) a.img_bf16 = moving;
+    else a.img = moving;
+    a.iw_out = last ? warped : iw;
+    a.vel_out = velocities ? velocities + (size_t)c * 3 * V : nullptr;
+    HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_pass_c(g, pl.x, tb, kBf16 ? kComposeBf16 : kCompose, a, st, batch); }));
+    u_src = a.out;
   }
   return NADMM_OK;
 }
@@ -269,68 +353,33 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p, const float* fi
                             const float* moving, const float* init_disp, float* disp,
                             float* warped, float* velocities, void* workspace,
                             size_t workspace_bytes, void* stream) {
-  CHECK(check_dims(d));
-  CHECK(check_params(p, true));
-  CHECK(check_ptr(fixed, "fixed", false));
-  CHECK(check_ptr(moving, "moving", false));
-  CHECK(check_ptr(init_disp, "init_disp", true));
-  CHECK(check_ptr(disp, "disp", false));
-  CHECK(check_ptr(warped, "warped", true));
-  CHECK(check_ptr(velocities, "velocities", true));
-  CHECK(check_ws(d, workspace, workspace_bytes));
-  const Geo g = geo(d);
-  const Plans pl = plans(d);
-  const Layout L = layout(d);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t V = (size_t)g.V;
-  float* J = at<float>(workspace, L.J);
-  float* r = at<float>(workspace, L.r);
-  float* iw = at<float>(workspace, L.iw);
-  float* S1 = at<float>(workspace, L.s1);
-  float* S2 = at<float>(workspace, L.s2);
-  float2* X = at<float2>(workspace, L.X);
-  float* U = at<float>(workspace, L.u);
-  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
-  HIP_TRY(launch_tables(g, tb, st));
+  return register_impl(d, p, fixed, moving, init_disp, disp, warped, velocities, workspace,
+                       workspace_bytes, stream, 1);
+}
 
-  // Displacement buffers alternate between U and disp so that the last
-  // warping writes disp.
-  auto dst_of = [&](int c) { return ((p->outer - 1 - c) % 2 == 0) ? disp : U; };
-  const float* u_src;
-  if (init_disp) {
-    u_src = init_disp;
-  } else {
-    float* z = (p->outer > 0 && dst_of(0) == disp) ? U : disp;
-    HIP_TRY(timed(KK_FILL, st, [&] { return launch_fill(z, 0.0f, 3 * V, st); }));
-    u_src = z;
-  }
-  if (p->outer == 0) {
-    if (u_src != disp) HIP_TRY(hipMemcpyAsync(disp, u_src, 3 * V * sizeof(float),
-                                              hipMemcpyDeviceToDevice, st));
-    if (warped) HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, disp, warped, st); }));
-    return NADMM_OK;
-  }
-  HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, u_src, iw, st); }));
-  for (int c = 0; c < p->outer; ++c) {
-    const bool last = (c == p->outer - 1);
-    // linearised data term at the current warp, and s^0 (Eq. (6) from zero)
-    HIP_TRY(timed(KK_GRAD, st, [&] { return launch_grad_resid(g, iw, fixed, J, r, S1, (float)p->theta, (float)p->eps,
-                              p->data_term, st); }));
-    float* cur = S1;
-    float* prev = S2;
-    CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, nullptr, st));
-    // final w = S s^{K-1}, composed onto the displacement
-    PassCArgs a{};
-    a.X = X;
-    a.out = dst_of(c);
-    a.u_old = u_src;
-    a.img = moving;
-    a.iw_out = last ? warped : iw;
-    a.vel_out = velocities ? velocities + (size_t)c * 3 * V : nullptr;
-    HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_pass_c(g, pl.x, tb, kCompose, a, st); }));
-    u_src = a.out;
-  }
+nadmm_status nadmm_register_bf16(nadmm_dims d, const nadmm_params* p, const uint16_t* fixed,
+                                 const uint16_t* moving, const float* init_disp, float* disp,
+                                 float* warped, float* velocities, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+  return register_impl(d, p, fixed, moving, init_disp, disp, warped, velocities, workspace,
+                       workspace_bytes, stream, 1);
+}
+
+nadmm_status nadmm_workspace_size_batch(nadmm_dims d, int32_t batch, size_t* bytes) {
+  if (!bytes) return fail(NADMM_ERR_INVALID_ARG, "bytes is NULL");
+  CHECK(check_dims(d));
+  CHECK(check_batch(batch));
+  *bytes = layout(d, batch).total;
   return NADMM_OK;
+}
+
+nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_params* p,
+                                  const float* fixed, const float* moving,
+                                  const float* init_disp, float* disp, float* warped,
+                                  void* workspace, size_t workspace_bytes, void* stream) {
+  CHECK(check_batch(batch));
+  return register_impl(d, p, fixed, moving, init_disp, disp, warped, nullptr, workspace,
+                       workspace_bytes, stream, batch);
 }
 
 nadmm_status nadmm_admm(nadmm_dims d, const nadmm_params* p, const float* J, const float* r,

@@ -50,6 +50,11 @@ struct FftPlan {
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// a * b (INV false) or a * conj(b) (INV true)
+template <bool INV>
+__device__ __forceinline__ float2 cmul_tw(float2 a, float2 b) {
+  return INV ? make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y) : cmul(a, b);
+}
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -149,6 +154,33 @@ constexpr double ct_reduce(int m, int R) {  // angle of 2 pi m / R folded into [
 constexpr double ct_cos(int m, int R) { return ct_cos_red(ct_reduce(m, R)); }
 constexpr double ct_sin(int m, int R) { return ct_cos_red(ct_reduce(m, R) - kTwoPi / 4.0); }
 
+// a * exp(-+ 2 pi i m / R) for a compile-time m: quarter turns are exact
+// swaps and negations, eighth turns use the single constant sqrt(1/2), other
+// angles a complex multiply by constants rounded once from the series above.
+template <int R, bool INV>
+__device__ __forceinline__ float2 ctwiddle(float2 a, int m) {
+  const int q8 = ((m % R) + R) % R * 8;  // angle in eighths of a turn when q8 % R == 0
+  if (q8 % R == 0) {
+    // forward turns clockwise: exp(-i pi e / 4); inverse counter-clockwise
+    const int e = INV ? (8 - q8 / R) % 8 : q8 / R;
+    const float h = 0.70710678118654752f;
+    switch (e) {
+      case 0: return a;
+      case 1: return make_float2(h * (a.x + a.y), h * (a.y - a.x));
+      case 2: return make_float2(a.y, -a.x);
+      case 3: return make_float2(h * (a.y - a.x), -h * (a.x + a.y));
+      case 4: return make_float2(-a.x, -a.y);
+      case 5: return make_float2(-h * (a.x + a.y), h * (a.x - a.y));
+      case 6: return make_float2(-a.y, a.x);
+      default: return make_float2(h * (a.x - a.y), h * (a.x + a.y));
+    }
+  }
+  const float c = (float)ct_cos(m, R);
+  const float sn = (float)ct_sin(m, R);
+  // forward: exp(-i 2 pi m / R) = (c, -sn); inverse: (c, sn)
+  return cmul(a, make_float2(c, INV ? sn : -sn));
+}
+
 // Composite in-register DFT of length R1*R2 (Cooley-Tukey with
 // n = R2 n1 + n2, k = k1 + R1 k2): R2 DFTs of length R1, constant twiddles
 // W_R^{n2 k1}, R1 DFTs of length R2.
@@ -166,12 +198,7 @@ struct DftComposite {
 #pragma unroll
     for (int n2 = 1; n2 < R2; ++n2) {
 #pragma unroll
-      for (int k1 = 1; k1 < R1; ++k1) {
-        const float c = (float)ct_cos(n2 * k1, R);
-        const float sn = (float)ct_sin(n2 * k1, R);
-        // forward: exp(-i 2 pi m / R) = (c, -sn); inverse: (c, sn)
-        a[n2][k1] = cmul(a[n2][k1], make_float2(c, INV ? sn : -sn));
-      }
+      for (int k1 = 1; k1 < R1; ++k1) a[n2][k1] = ctwiddle<R, INV>(a[n2][k1], n2 * k1);
     }
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) {
@@ -196,7 +223,7 @@ struct Dft<16, INV> : DftComposite<4, 4, INV> {};
 // follows every 2^PADSH elements (breaks the stride-R writes of early
 // Stockham stages across LDS banks).
 template <int PADSH>
-__device__ __forceinline__ int lpad(int e) {
+__host__ __device__ __forceinline__ int lpad(int e) {
   return PADSH > 0 ? e + (e >> PADSH) : e;
 }
 
@@ -246,9 +273,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, const float2* tw, const F
         const int step = k * twstride;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * step];
-          if (INV) w.y = -w.y;
-          v[i][r] = cmul(v[i][r], w);
+          v[i][r] = cmul_tw<INV>(v[i][r], tw[r * step]);
         }
       }
       Dft<R, INV>::run(v[i]);
@@ -361,9 +386,7 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int 
         const int step = k * TWS;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * step];
-          if (INV) w.y = -w.y;
-          v[i][r] = cmul(v[i][r], w);
+          v[i][r] = cmul_tw<INV>(v[i][r], tw[r * step]);
         }
       }
       Dft<R, INV>::run(v[i]);
@@ -490,9 +513,7 @@ __device__ __forceinline__ void team_compute(const float2* tw, const FftStage& s
     const int step = k * s.twstride;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      float2 w = tw[r * step];
-      if (INV) w.y = -w.y;
-      v[r] = cmul(v[r], w);
+      v[r] = cmul_tw<INV>(v[r], tw[r * step]);
     }
   }
   Dft<R, INV>::run(v);

@@ -43,6 +43,9 @@ struct XDivs {
   FastDiv ny, nz;
 };
 XDivs make_xdivs(const Geo& g);
+// True when a y-z plane of the half spectrum fits one workgroup's LDS (pass B
+// in one launch); otherwise pass B runs as three launches (rows, columns, rows).
+bool plane_fits(const Geo& g);
 // True when every kernel's compile-time per-thread bounds hold for these sizes.
 bool launch_shape_ok(const Geo& g);
 // Per-thread item bounds the batched loads are compiled for (checked on the host).
@@ -68,7 +71,8 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 // kIterFwd: the data step and s^k, followed on the same x-lines by pass A of
 // the next solve (t' = s^k + gamma_next (s^k - s^{k-1}) transformed along x
 // and written back over the spectrum the pass read).
-enum PassCMode { kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3 };
+// kComposeBf16 is kCompose with the moving image stored as bfloat16.
+enum PassCMode { kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4 };
 
 struct PassCArgs {
   float2* X;         // read; kIterFwd also writes the next half spectrum here
@@ -86,26 +90,37 @@ struct PassCArgs {
   float* b_out;      // kFinalWB: optional b
   const float* u_old;  // kCompose: displacement before this warping
   const float* img;    // kCompose: moving image
+  const uint16_t* img_bf16;  // kComposeBf16: moving image (bfloat16 bit patterns)
   float* iw_out;       // kCompose: optional moving(x + u_new(x))
   float* vel_out;      // kCompose: optional velocity of this warping
 };
 
 hipError_t launch_fill(float* p, float value, size_t n, hipStream_t st);
 hipError_t launch_scale(const float* in, float* out, float s, size_t n, hipStream_t st);
-hipError_t launch_warp(const Geo& g, const float* img, const float* disp, float* out, hipStream_t st);
+// Images are float32 or bfloat16 (uint16_t bit patterns, widened exactly to
+// float32 on load); every other field is float32.
+// `batch` pairs of one size stored back to back (see kernels.hip); the
+// warp, gradient and pass launches cover all of them.
+hipError_t launch_warp(const Geo& g, const float* img, const float* disp, float* out,
+                       hipStream_t st, int batch = 1);
+hipError_t launch_warp(const Geo& g, const uint16_t* img, const float* disp, float* out,
+                       hipStream_t st, int batch = 1);
 // grad (3V, optional), resid (optional, needs ref), s0 (3V, optional: the
 // first ADMM iterate v^0 = b^0-free data step from zero, needs ref).
 hipError_t launch_grad_resid(const Geo& g, const float* iw, const float* ref, float* grad,
                              float* resid, float* s0, float theta, float eps, int data_term,
-                             hipStream_t st);
+                             hipStream_t st, int batch = 1);
+hipError_t launch_grad_resid(const Geo& g, const float* iw, const uint16_t* ref, float* grad,
+                             float* resid, float* s0, float theta, float eps, int data_term,
+                             hipStream_t st, int batch = 1);
 hipError_t launch_admm_init(const Geo& g, const float* J, const float* r, float* s0, float* v_out,
                             float theta, float eps, int data_term, hipStream_t st);
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
-                         const float* s2, float gamma, float2* X, hipStream_t st);
+                         const float* s2, float gamma, float2* X, hipStream_t st, int batch = 1);
 hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
-                         int order, hipStream_t st);
+                         int order, hipStream_t st, int batch = 1);
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
-                         const PassCArgs& a, hipStream_t st);
+                         const PassCArgs& a, hipStream_t st, int batch = 1);
 hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out, hipStream_t st);
 hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* partial,
                            double* stats, int64_t* n_nonpos, hipStream_t st);

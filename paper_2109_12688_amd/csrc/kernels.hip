@@ -173,6 +173,8 @@ static int plane_team_threads(const Geo& g) {
   return 64 * w;
 }
 
+static bool split_shape_ok(const Geo& g);
+
 bool launch_shape_ok(const Geo& g) {
   if (g.nx % 4 || g.ny % 2) return false;
   const int yb = xline_rows(g.ny), xt = xline_threads(g), pt = plane_threads(g);
@@ -181,12 +183,16 @@ bool launch_shape_ok(const Geo& g) {
   const bool fft_a = 3 * (yb / 2) * g.nx <= kEpt * xt;       // x-line FFT elements per thread
   const bool load_a = 3 * yb * (g.nx / 4) <= kXItems * xt;    // pass A float4 loads
   const bool point_c = yb * (g.nx / 4) <= 2 * xt;             // pass C float4 runs
-  const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
-  const bool fft_b = ty.nstages > 0 && tz.nstages > 0;        // wave-team plans exist
   (void)pt;
-  const bool load_b = plane_lds_bytes(g, plane_row_stride(g)) <= (size_t)kMaxLds;  // plane fits in LDS
-  const bool div_ok = g.ny * g.nz < 65536 && 3 * yb * g.nx < 65536;  // FastDiv range
-  return fft_a && load_a && point_c && fft_b && load_b && div_ok;
+  const bool div_x = 3 * yb * g.nx < 65536;  // FastDiv range of the x-line index maps
+  bool pass_b;
+  if (plane_fits(g)) {
+    const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
+    pass_b = ty.nstages > 0 && tz.nstages > 0 && g.ny * g.nz < 65536;  // team plans, FastDiv range
+  } else {
+    pass_b = split_shape_ok(g);
+  }
+  return fft_a && load_a && point_c && pass_b && div_x;
 }
 
 XDivs make_xdivs(const Geo& g) {
@@ -245,11 +251,18 @@ __device__ __forceinline__ Tap make_tap(int x, int y, int z, float ux, float uy,
   return t;
 }
 
-__device__ __forceinline__ float sample(const float* __restrict__ f, const Tap& t) {
-  const float c00 = lerpf(f[t.o000], f[t.o100], t.tx);
-  const float c10 = lerpf(f[t.o010], f[t.o110], t.tx);
-  const float c01 = lerpf(f[t.o001], f[t.o101], t.tx);
-  const float c11 = lerpf(f[t.o011], f[t.o111], t.tx);
+// Image element as float32: bfloat16 is the upper half of a float32.
+__device__ __forceinline__ float img_at(const float* __restrict__ f, int i) { return f[i]; }
+__device__ __forceinline__ float img_at(const uint16_t* __restrict__ f, int i) {
+  return __uint_as_float((uint32_t)f[i] << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float sample(const T* __restrict__ f, const Tap& t) {
+  const float c00 = lerpf(img_at(f, t.o000), img_at(f, t.o100), t.tx);
+  const float c10 = lerpf(img_at(f, t.o010), img_at(f, t.o110), t.tx);
+  const float c01 = lerpf(img_at(f, t.o001), img_at(f, t.o101), t.tx);
+  const float c11 = lerpf(img_at(f, t.o011), img_at(f, t.o111), t.tx);
   return lerpf(lerpf(c00, c10, t.ty), lerpf(c01, c11, t.ty), t.tz);
 }
 
@@ -272,6 +285,20 @@ __device__ __forceinline__ void data_step(const float a[3], const float j[3], fl
   v[0] = a[0] - j[0] * f;
   v[1] = a[1] - j[1] * f;
   v[2] = a[2] - j[2] * f;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: pairs of one size are stored back to back in every buffer (a
+// scalar volume every V floats, a vector field every 3V, a half spectrum
+// every 3 (nx/2+1) ny nz complex); the pair of a workgroup is its last grid
+// index, and the kernels offset their pointers by it.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ size_t spectrum_elems(const Geo& g) {
+  return (size_t)3 * (g.nx / 2 + 1) * g.ny * g.nz;
+}
+template <typename P>
+__device__ __forceinline__ P* at_pair(P* p, size_t stride, int b) {
+  return p ? p + stride * (size_t)b : p;
 }
 
 // ---------------------------------------------------------------------------
@@ -307,27 +334,48 @@ hipError_t launch_scale(const float* in, float* out, float s, size_t n, hipStrea
 }
 
 // out(x) = img(x + disp(x))
-__global__ void k_warp(Geo g, const float* __restrict__ img, const float* __restrict__ disp,
+template <typename T>
+__global__ void k_warp(Geo g, const T* __restrict__ img, const float* __restrict__ disp,
                        float* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
+  img = at_pair(img, g.V, blockIdx.y);
+  disp = at_pair(disp, 3 * (size_t)g.V, blockIdx.y);
+  out = at_pair(out, g.V, blockIdx.y);
   const int x = i % g.nx, y = (i / g.nx) % g.ny, z = i / (g.nx * g.ny);
   const Tap t = make_tap(x, y, z, disp[i], disp[g.V + i], disp[2 * g.V + i], g);
   out[i] = sample(img, t);
 }
 
-hipError_t launch_warp(const Geo& g, const float* img, const float* disp, float* out,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_warp, dim3((g.V + 255) / 256), dim3(256), 0, st, g, img, disp, out);
+template <typename T>
+static hipError_t warp_any(const Geo& g, const T* img, const float* disp, float* out,
+                           hipStream_t st, int batch) {
+  hipLaunchKernelGGL(k_warp<T>, dim3((g.V + 255) / 256, batch), dim3(256), 0, st, g, img, disp,
+                     out);
   return hipGetLastError();
+}
+hipError_t launch_warp(const Geo& g, const float* img, const float* disp, float* out,
+                       hipStream_t st, int batch) {
+  return warp_any(g, img, disp, out, st, batch);
+}
+hipError_t launch_warp(const Geo& g, const uint16_t* img, const float* disp, float* out,
+                       hipStream_t st, int batch) {
+  return warp_any(g, img, disp, out, st, batch);
 }
 
 // J = central differences of iw (periodic), r = iw - ref, s0 = data step from a = 0.
-__global__ void k_grad_resid(Geo g, const float* __restrict__ iw, const float* __restrict__ ref,
+template <typename T>
+__global__ void k_grad_resid(Geo g, const float* __restrict__ iw, const T* __restrict__ ref,
                              float* __restrict__ grad, float* __restrict__ resid,
                              float* __restrict__ s0, float theta, float eps, int data_term) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
+  const int b = blockIdx.y;
+  iw = at_pair(iw, g.V, b);
+  ref = at_pair(ref, g.V, b);
+  grad = at_pair(grad, 3 * (size_t)g.V, b);
+  resid = at_pair(resid, g.V, b);
+  s0 = at_pair(s0, 3 * (size_t)g.V, b);
   const int x = i % g.nx, y = (i / g.nx) % g.ny, z = i / (g.nx * g.ny);
   const int sy = g.nx, sz = g.nx * g.ny;
   const int xp = (x + 1 == g.nx) ? i - x : i + 1;
@@ -346,7 +394,7 @@ __global__ void k_grad_resid(Geo g, const float* __restrict__ iw, const float* _
     grad[2 * g.V + i] = j[2];
   }
   if (ref) {
-    const float r = iw[i] - ref[i];
+    const float r = iw[i] - img_at(ref, i);
     if (resid) resid[i] = r;
     if (s0) {
       const float a[3] = {0.f, 0.f, 0.f};
@@ -359,12 +407,23 @@ __global__ void k_grad_resid(Geo g, const float* __restrict__ iw, const float* _
   }
 }
 
+template <typename T>
+static hipError_t grad_resid_any(const Geo& g, const float* iw, const T* ref, float* grad,
+                                 float* resid, float* s0, float theta, float eps, int data_term,
+                                 hipStream_t st, int batch) {
+  hipLaunchKernelGGL(k_grad_resid<T>, dim3((g.V + 255) / 256, batch), dim3(256), 0, st, g, iw,
+                     ref, grad, resid, s0, theta, eps, data_term);
+  return hipGetLastError();
+}
 hipError_t launch_grad_resid(const Geo& g, const float* iw, const float* ref, float* grad,
                              float* resid, float* s0, float theta, float eps, int data_term,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_resid, dim3((g.V + 255) / 256), dim3(256), 0, st, g, iw, ref, grad,
-                     resid, s0, theta, eps, data_term);
-  return hipGetLastError();
+                             hipStream_t st, int batch) {
+  return grad_resid_any(g, iw, ref, grad, resid, s0, theta, eps, data_term, st, batch);
+}
+hipError_t launch_grad_resid(const Geo& g, const float* iw, const uint16_t* ref, float* grad,
+                             float* resid, float* s0, float theta, float eps, int data_term,
+                             hipStream_t st, int batch) {
+  return grad_resid_any(g, iw, ref, grad, resid, s0, theta, eps, data_term, st, batch);
 }
 
 // s^0 (and optionally v^0) from given J, r: the data step from a = 0.
@@ -537,6 +596,9 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
                                                 float2* __restrict__ X) {
   extern __shared__ float2 lds[];
   const int nx = NX ? NX : g.nx, q4 = nx / 4;
+  s1 = at_pair(s1, 3 * (size_t)g.V, blockIdx.z);
+  s2 = at_pair(s2, 3 * (size_t)g.V, blockIdx.z);
+  X = at_pair(X, spectrum_elems(g), blockIdx.z);
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   float2* tw = lds;
   float2* buf = lds + nx;
@@ -597,9 +659,9 @@ static size_t pass_a_lds(const Geo& g) {
 }
 
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
-                         const float* s2, float gamma, float2* X, hipStream_t st) {
+                         const float* s2, float gamma, float2* X, hipStream_t st, int batch) {
   const int yb = xline_rows(g.ny);
-  const dim3 grid(g.ny / yb, g.nz), block(xline_threads(g));
+  const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads(g));
   const size_t lds = pass_a_lds(g);
   const XDivs xd = make_xdivs(g);
   const int ls = xline_stride(g.nx);
@@ -701,7 +763,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   float* sz = sy + ny;
   float2* buf = reinterpret_cast<float2*>(sz + nz + ((ny + nz) & 1));  // keep 8-byte alignment
   const int p = blockIdx.x, c = blockIdx.y;
-  float2* plane = X + (size_t)(c * np + p) * nz * ny;
+  float2* plane = at_pair(X, spectrum_elems(g), blockIdx.z) + (size_t)(c * np + p) * nz * ny;
   const float4* plane4 = reinterpret_cast<const float4*>(plane);
   // the x transform of pass A already carries 1 / nx of the inverse's 1 / V
   const float inv_v = 1.0f / (float)(ny * nz);
@@ -833,12 +895,199 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   }
 }
 
+// ---------------------------------------------------------------------------
+// pass B for y-z planes larger than one workgroup's LDS: three launches over
+// the same half spectrum -- the forward y transform of every row, then per
+// group of W columns the forward z transform, the spectral multiply and the
+// inverse z transform, then the inverse y transform of every row.
+// ---------------------------------------------------------------------------
+template <int N, bool INV>
+__device__ __forceinline__ void line_transform(float2* buf, const float2* tw, const FftPlan& plan,
+                                               const FastDiv& dl, int ls) {
+  if constexpr (N > 0)
+    fft_lines_ct<N, kEpt, INV, 4>(buf, tw, (int)dl.d, ls);
+  else
+    fft_lines<kEpt, INV, false, 4>(buf, tw, plan, dl, 1, ls);
+}
+
+// dl.d rows (contiguous ny complex each) of the half spectrum per
+// workgroup; rows are numbered over (component, plane, z).
+template <int NY, bool INV>
+__global__ void __launch_bounds__(256) k_split_rows(Geo g, FftPlan py, FastDiv dl, FastDiv dq,
+                                                     const float2* __restrict__ twy,
+                                                     float2* __restrict__ X) {
+  extern __shared__ float2 lds[];
+  const int ny = NY ? NY : g.ny, ls = lpad<4>(ny - 1) + 1, half = ny / 2;
+  float2* tw = lds;
+  float2* buf = lds + ny;
+  const int nthr = blockDim.x;
+  const int rows = (int)dl.d;
+  float4* base = reinterpret_cast<float4*>(at_pair(X, spectrum_elems(g), blockIdx.y) +
+                                           (size_t)blockIdx.x * rows * ny);
+  for (int i = threadIdx.x; i < ny; i += nthr) tw[i] = twy[i];
+  const int items = rows * half;  // float4 = two complex of one row
+  for (int idx = threadIdx.x; idx < items; idx += nthr) {
+    const int row = NY ? idx / (NY / 2) : (int)fdiv((uint32_t)idx, dq);
+    const int e = 2 * (idx - row * half);
+    const float4 v = base[idx];
+    float2* d = buf + row * ls + lpad<4>(e);  // e even: e and e + 1 share a padding group
+    d[0] = make_float2(v.x, v.y);
+    d[1] = make_float2(v.z, v.w);
+  }
+  __syncthreads();
+  line_transform<NY, INV>(buf, tw, py, dl, ls);
+  for (int idx = threadIdx.x; idx < items; idx += nthr) {
+    const int row = NY ? idx / (NY / 2) : (int)fdiv((uint32_t)idx, dq);
+    const int e = 2 * (idx - row * half);
+    const float2* d = buf + row * ls + lpad<4>(e);
+    base[idx] = make_float4(d[0].x, d[0].y, d[1].x, d[1].y);
+  }
+}
+
+// W columns (a power of two dividing ny) of one (component, plane): z lines
+// of nz complex with stride ny in memory, transposed into LDS lines on load.
+template <int NZ>
+__global__ void __launch_bounds__(256) k_split_cols(Geo g, FftPlan pz, FastDiv dl, FastDiv dz,
+                                                     Tables t, float2* __restrict__ X,
+                                                     float lambda, float theta, int order) {
+  extern __shared__ float2 lds[];
+  const int ny = g.ny, nz = NZ ? NZ : g.nz, ls = lpad<4>(nz - 1) + 1, np = g.nx / 2 + 1;
+  const int W = (int)dl.d, hw = W / 2;
+  float2* tw = lds;
+  float* szl = reinterpret_cast<float*>(tw + nz);
+  float2* buf = reinterpret_cast<float2*>(szl + nz + (nz & 1));
+  const int nthr = blockDim.x;
+  const int q0 = blockIdx.x * W, p = blockIdx.y, c = blockIdx.z % 3;
+  float2* plane = at_pair(X, spectrum_elems(g), blockIdx.z / 3) + (size_t)(c * np + p) * nz * ny;
+  for (int i = threadIdx.x; i < nz; i += nthr) {
+    tw[i] = t.twz[i];
+    szl[i] = t.sz[i];
+  }
+  const int hs = __ffs(hw) - 1;  // W is a power of two: idx / hw == idx >> hs
+  const int items = nz * hw;     // float4 = columns q0 + 2j, q0 + 2j + 1 of row rr
+  for (int idx = threadIdx.x; idx < items; idx += nthr) {
+    const int rr = idx >> hs, jj = idx - (rr << hs);
+    const float4 v = *reinterpret_cast<const float4*>(plane + (size_t)rr * ny + q0 + 2 * jj);
+    buf[(2 * jj) * ls + lpad<4>(rr)] = make_float2(v.x, v.y);
+    buf[(2 * jj + 1) * ls + lpad<4>(rr)] = make_float2(v.z, v.w);
+  }
+  __syncthreads();
+  line_transform<NZ, false>(buf, tw, pz, dl, ls);
+  // multiply by theta / (theta + lambda K^n) / (ny nz); pass A carried 1 / nx
+  const float inv = 1.0f / (float)(ny * nz), kx = t.sx[p];
+  for (int idx = threadIdx.x; idx < W * nz; idx += nthr) {
+    const int l = NZ ? idx / NZ : (int)fdiv((uint32_t)idx, dz);
+    const int r = idx - l * nz;
+    const float k0 = kx + t.sy[q0 + l] + szl[r];
+    float kn = k0;
+    for (int i = 1; i < order; ++i) kn *= k0;
+    const float m = theta * inv * __builtin_amdgcn_rcpf(theta + lambda * kn);
+    float2& e = buf[l * ls + lpad<4>(r)];
+    e = make_float2(e.x * m, e.y * m);
+  }
+  __syncthreads();
+  line_transform<NZ, true>(buf, tw, pz, dl, ls);
+  for (int idx = threadIdx.x; idx < items; idx += nthr) {
+    const int rr = idx >> hs, jj = idx - (rr << hs);
+    const float2 a = buf[(2 * jj) * ls + lpad<4>(rr)], b = buf[(2 * jj + 1) * ls + lpad<4>(rr)];
+    *reinterpret_cast<float4*>(plane + (size_t)rr * ny + q0 + 2 * jj) = make_float4(a.x, a.y, b.x, b.y);
+  }
+}
+
+// Shapes of the split pass B: rows per row workgroup (divides the row count
+// 3 (nx/2 + 1) nz) and columns per column workgroup (a power of two <= 16
+// dividing ny); at most 256 threads, at most kEpt points per thread.
+struct SplitShape {
+  int rb, rows_threads, w, cols_threads;
+};
+static SplitShape split_shape(const Geo& g) {
+  SplitShape sh{1, 64, 2, 64};
+  const long total = 3L * (g.nx / 2 + 1) * g.nz;
+  for (int rb = 8; rb >= 1; rb /= 2)
+    if (total % rb == 0 && rb * g.ny <= kEpt * 256) {
+      sh.rb = rb;
+      break;
+    }
+  for (int w = 16; w >= 2; w /= 2)
+    if (g.ny % w == 0 && w * g.nz <= kEpt * 256) {
+      sh.w = w;
+      break;
+    }
+  auto threads = [](int elems) {
+    int t = round_up((elems + 7) / 8, 64);
+    return t > 256 ? 256 : (t < 64 ? 64 : t);
+  };
+  sh.rows_threads = threads(sh.rb * g.ny);
+  sh.cols_threads = threads(sh.w * g.nz);
+  return sh;
+}
+static size_t split_rows_lds(const Geo& g, const SplitShape& sh) {
+  return sizeof(float2) * ((size_t)g.ny + (size_t)sh.rb * (lpad<4>(g.ny - 1) + 1));
+}
+static size_t split_cols_lds(const Geo& g, const SplitShape& sh) {
+  return sizeof(float2) * (size_t)g.nz + sizeof(float) * (size_t)(g.nz + (g.nz & 1)) +
+         sizeof(float2) * (size_t)sh.w * (lpad<4>(g.nz - 1) + 1);
+}
+
+bool plane_fits(const Geo& g) {
+  return g.ny * g.nz <= 16384 && plane_lds_bytes(g, plane_row_stride(g)) <= (size_t)kMaxLds;
+}
+
+static bool split_shape_ok(const Geo& g) {
+  const SplitShape sh = split_shape(g);
+  const FftPlan py = make_plan(g.ny), pz = make_plan(g.nz);
+  return py.nstages > 0 && pz.nstages > 0 && sh.rb * g.ny <= kEpt * sh.rows_threads &&
+         g.ny % sh.w == 0 && sh.w * g.nz <= kEpt * sh.cols_threads &&
+         split_rows_lds(g, sh) <= (size_t)kMaxLds && split_cols_lds(g, sh) <= (size_t)kMaxLds;
+}
+
+static hipError_t launch_pass_b_split(const Geo& g, const Tables& t, float2* X, float lambda,
+                                      float theta, int order, hipStream_t st, int batch) {
+  const SplitShape sh = split_shape(g);
+  const FftPlan py = make_plan(g.ny), pz = make_plan(g.nz);
+  const int np = g.nx / 2 + 1;
+  const dim3 rgrid((unsigned)(3L * np * g.nz / sh.rb), batch), rblock(sh.rows_threads);
+  const dim3 cgrid(g.ny / sh.w, np, 3 * batch), cblock(sh.cols_threads);
+  const size_t rlds = split_rows_lds(g, sh), clds = split_cols_lds(g, sh);
+  const FastDiv drows = make_fastdiv(sh.rb), dhalf = make_fastdiv(g.ny / 2);
+  const FastDiv dw = make_fastdiv(sh.w), dz = make_fastdiv(g.nz);
+#define NADMM_ROWS(N, INV)                                                                    \
+  hipLaunchKernelGGL((k_split_rows<N, INV>), rgrid, rblock, rlds, st, g, py, drows, dhalf, t.twy, X)
+#define NADMM_ROWS_NY(INV)               \
+  switch (g.ny) {                        \
+    case 128: NADMM_ROWS(128, INV); break; \
+    case 192: NADMM_ROWS(192, INV); break; \
+    case 256: NADMM_ROWS(256, INV); break; \
+    default: NADMM_ROWS(0, INV); break;    \
+  }
+#define NADMM_COLS(N) \
+  hipLaunchKernelGGL((k_split_cols<N>), cgrid, cblock, clds, st, g, pz, dw, dz, t, X, lambda, theta, order)
+  NADMM_ROWS_NY(false);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (g.nz) {
+    case 96: NADMM_COLS(96); break;
+    case 128: NADMM_COLS(128); break;
+    case 192: NADMM_COLS(192); break;
+    case 256: NADMM_COLS(256); break;
+    default: NADMM_COLS(0); break;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  NADMM_ROWS_NY(true);
+#undef NADMM_COLS
+#undef NADMM_ROWS_NY
+#undef NADMM_ROWS
+  return hipGetLastError();
+}
+
 static size_t pass_b_lds(const Geo& g) { return plane_lds_bytes(g, plane_row_stride(g)); }
 
 hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
-                         int order, hipStream_t st) {
+                         int order, hipStream_t st, int batch) {
+  if (!plane_fits(g)) return launch_pass_b_split(g, t, X, lambda, theta, order, st, batch);
   const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
-  const dim3 grid(g.nx / 2 + 1, 3), block(plane_team_threads(g));
+  const dim3 grid(g.nx / 2 + 1, 3, batch), block(plane_team_threads(g));
   const size_t lds = pass_b_lds(g);
   const XDivs xd = make_xdivs(g);
   const int rs = plane_row_stride(g);
@@ -876,6 +1125,23 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
                                                 const float2* __restrict__ twx, PassCArgs a) {
   extern __shared__ float2 lds[];
   const int nx = NX ? NX : g.nx, nh = nx / 2, q4 = nx / 4;
+  {
+    const int b = blockIdx.z;
+    const size_t v1 = g.V, v3 = 3 * (size_t)g.V;
+    a.X = at_pair(a.X, spectrum_elems(g), b);
+    a.s1 = at_pair(a.s1, v3, b);
+    a.s2 = at_pair(a.s2, v3, b);
+    a.J = at_pair(a.J, v3, b);
+    a.r = at_pair(a.r, v1, b);
+    a.out = at_pair(a.out, v3, b);
+    a.v_out = at_pair(a.v_out, v3, b);
+    a.b_out = at_pair(a.b_out, v3, b);
+    a.u_old = at_pair(a.u_old, v3, b);
+    a.img = at_pair(a.img, v1, b);
+    a.img_bf16 = at_pair(a.img_bf16, v1, b);
+    a.iw_out = at_pair(a.iw_out, v1, b);
+    a.vel_out = at_pair(a.vel_out, v3, b);
+  }
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   const int nthr = blockDim.x;
   float2* tw = lds;
@@ -1037,7 +1303,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
         }
       }
     }
-  } else {  // kCompose: u_new = w + u_old(x + w), optional warped image
+  } else {  // kCompose(Bf16): u_new = w + u_old(x + w), optional warped image
 #pragma unroll
     for (int it = 0; it < MI; ++it) {
       const int idx = threadIdx.x + it * nthr;
@@ -1056,7 +1322,8 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
           f4set(un[2], e, u2);
           if (a.iw_out) {
             const Tap t2 = make_tap(4 * x4 + e, y0 + yy, z, u0, u1, u2, g);
-            f4set(iw, e, sample(a.img, t2));
+            if constexpr (MODE == kComposeBf16) f4set(iw, e, sample(a.img_bf16, t2));
+            else f4set(iw, e, sample(a.img, t2));
           }
         }
 #pragma unroll
@@ -1071,9 +1338,9 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
 }
 
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
-                         const PassCArgs& a, hipStream_t st) {
+                         const PassCArgs& a, hipStream_t st, int batch) {
   const int yb = xline_rows(g.ny);
-  const dim3 grid(g.ny / yb, g.nz), block(xline_threads(g));
+  const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads(g));
   const size_t lds = pass_a_lds(g);
   const XDivs xd = make_xdivs(g);
   const int ls = xline_stride(g.nx);
@@ -1092,6 +1359,7 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
     case kOutY: NADMM_PASS_C_NX(kOutY); break;
     case kIterFwd: NADMM_PASS_C_NX(kIterFwd); break;
     case kFinalWB: NADMM_PASS_C_NX(kFinalWB); break;
+    case kComposeBf16: NADMM_PASS_C_NX(kComposeBf16); break;
     default: NADMM_PASS_C_NX(kCompose); break;
   }
 #undef NADMM_PASS_C_NX

@@ -238,6 +238,19 @@ def random_vector_field(dims_xyz, seed: int, amp: float = 1.0,
 
 
 # named workloads ------------------------------------------------------------
+def bf16_bits(a: np.ndarray) -> np.ndarray:
+    """bfloat16 bit patterns of float32 values, rounded to nearest, ties to
+    even (finite inputs), as uint16."""
+    b = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return b.astype(np.uint16)
+
+
+def bf16_to_f32(bits: np.ndarray) -> np.ndarray:
+    """float32 values of bfloat16 bit patterns (exact)."""
+    return (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
 WORKLOADS = {
     # 32^3 blob pair, n=2, lambda=0.01, theta=0.1, 5 warpings x 10 iterations
     "blobs32": dict(dims=(32, 32, 32), seed=0, kind="blobs", max_disp=3.0,
@@ -245,6 +258,10 @@ WORKLOADS = {
     # 128x128x96 heart phantom, n=2, lambda=0.01, theta=0.1, 10 x 20
     "phantom128x128x96": dict(dims=(128, 128, 96), seed=1, kind="phantom", max_disp=8.0,
                               lam=0.01, theta=0.1, order=2, outer=10, iters=20),
+    # 192x192x128 heart phantom (geometry scaled with the volume), images
+    # stored as bfloat16 by the precision study; n=3, lambda=0.005, 10 x 30
+    "phantom192x192x128": dict(dims=(192, 192, 128), seed=4, kind="phantom", max_disp=8.0,
+                               lam=0.005, theta=0.1, order=3, outer=10, iters=30),
 }
 
 

@@ -1,12 +1,21 @@
-"""Writes the stored oracle expectations used by the full-size GPU parity test.
+"""Writes the stored oracle expectations used by the full-size GPU parity tests.
 
-Calls only the FP64 oracle (and the seeded input generators): it runs the
-whole 128x128x96 heart-phantom registration (10 warpings x 20 iterations,
-n = 2, lambda = 0.01, theta = 0.1) and stores, for a fixed seeded sample of
-voxels, the oracle's displacement and warped intensity, plus the Jacobian
-statistics of the whole displacement and a checksum of the inputs.
+Calls only the FP64 oracle (and the seeded input generators).
 
-    python tests/golden/make_golden.py        (about a minute on one core)
+* phantom128x128x96: the whole 128x128x96 heart-phantom registration
+  (10 warpings x 20 iterations, n = 2, lambda = 0.01, theta = 0.1) on the
+  float32 images.
+* phantom192x192x128: the 192x192x128 phantom (10 x 30, n = 3,
+  lambda = 0.005, theta = 0.1) whose images are stored as bfloat16: the
+  registration of the bfloat16-rounded images (what the GPU's bfloat16 path
+  must match), and of the float32 images (to report what the storage
+  precision costs).
+
+For each run: the displacement and warped intensity at a fixed seeded sample
+of voxels, the Jacobian statistics of the whole displacement, SSD before and
+after, and a checksum of the inputs.
+
+    python tests/golden/make_golden.py [phantom128x128x96 | phantom192x192x128]
 """
 import hashlib
 import json
@@ -21,14 +30,13 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle as O  # noqa: E402
 import synth  # noqa: E402
 
-NAME = "phantom128x128x96"
 NSAMPLE = 2048
 
 
-def input_digest(pair) -> str:
+def input_digest(fixed, moving) -> str:
     h = hashlib.sha256()
-    h.update(np.ascontiguousarray(pair.fixed, dtype=np.float32).tobytes())
-    h.update(np.ascontiguousarray(pair.moving, dtype=np.float32).tobytes())
+    h.update(np.ascontiguousarray(fixed).tobytes())
+    h.update(np.ascontiguousarray(moving).tobytes())
     return h.hexdigest()
 
 
@@ -37,34 +45,43 @@ def sample_indices(shape, n, seed=7):
     return np.sort(rng.choice(int(np.prod(shape)), size=n, replace=False))
 
 
-def main():
-    w = synth.WORKLOADS[NAME]
-    pair = synth.make_pair(NAME)
-    res = O.register(pair.fixed.astype(np.float64), pair.moving.astype(np.float64), w["lam"],
-                     w["theta"], w["order"], w["outer"], w["iters"])
-    idx = sample_indices(pair.fixed.shape, NSAMPLE)
-    disp = res.disp.reshape(3, -1)[:, idx]
-    warped = res.warped.reshape(-1)[idx]
+def run(w, fixed, moving, idx):
+    res = O.register(fixed.astype(np.float64), moving.astype(np.float64), w["lam"], w["theta"],
+                     w["order"], w["outer"], w["iters"])
     mn, mx, mean, nneg = O.jacobian_stats(res.disp)
-    out = {
-        "workload": NAME,
-        "source": "oracle.register (FP64 NumPy), whole registration; values at sampled voxels",
-        "params": {k: w[k] for k in ("lam", "theta", "order", "outer", "iters")},
-        "input_sha256": input_digest(pair),
-        "sample_seed": 7,
-        "indices": idx.tolist(),
-        "disp": [[float(f"{v:.10g}") for v in row] for row in disp],
-        "warped": [float(f"{v:.10g}") for v in warped],
+    return {
+        "disp": [[float(f"{v:.10g}") for v in row] for row in res.disp.reshape(3, -1)[:, idx]],
+        "warped": [float(f"{v:.10g}") for v in res.warped.reshape(-1)[idx]],
         "jacobian": {"min": mn, "max": mx, "mean": mean, "n_nonpos": nneg,
                      "n_abs_below_1e-2": int(np.count_nonzero(np.abs(O.jacobian_det(res.disp)) < 1e-2))},
-        "ssd_before": O.ssd(pair.fixed, pair.moving),
-        "ssd_after": O.ssd(pair.fixed, res.warped),
+        "ssd_before": O.ssd(fixed, moving),
+        "ssd_after": O.ssd(fixed, res.warped),
     }
-    path = os.path.join(HERE, f"{NAME}_oracle_samples.json")
+
+
+def main(name):
+    w = synth.WORKLOADS[name]
+    pair = synth.make_pair(name)
+    idx = sample_indices(pair.fixed.shape, NSAMPLE)
+    out = {"workload": name, "params": {k: w[k] for k in ("lam", "theta", "order", "outer", "iters")},
+           "sample_seed": 7, "indices": idx.tolist()}
+    if name == "phantom192x192x128":
+        fb, mb = synth.bf16_bits(pair.fixed), synth.bf16_bits(pair.moving)
+        out["source"] = ("oracle.register (FP64 NumPy), whole registration; 'bf16': on the "
+                         "bfloat16-rounded images, 'fp32': on the float32 images")
+        out["input_sha256"] = input_digest(fb, mb)
+        out["bf16"] = run(w, synth.bf16_to_f32(fb), synth.bf16_to_f32(mb), idx)
+        out["fp32"] = run(w, pair.fixed, pair.moving, idx)
+    else:
+        out["source"] = "oracle.register (FP64 NumPy), whole registration; values at sampled voxels"
+        out["input_sha256"] = input_digest(pair.fixed.astype(np.float32), pair.moving.astype(np.float32))
+        r = run(w, pair.fixed, pair.moving, idx)
+        out.update(r)
+    path = os.path.join(HERE, f"{name}_oracle_samples.json")
     with open(path, "w") as f:
         json.dump(out, f)
-    print(path, out["jacobian"], out["ssd_before"], out["ssd_after"])
+    print(path)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "phantom128x128x96")

@@ -27,7 +27,7 @@ def lib():
 def header_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nadmm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(nadmm_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_functions_are_exported(lib):
@@ -67,8 +67,15 @@ def test_workspace_size(lib):
     assert lib.nadmm_workspace_size(Dims(128, 128, 96), None, None) == 1
 
 
+@pytest.mark.parametrize("d", [(32, 256, 96), (192, 192, 128), (256, 256, 256), (12, 162, 128)])
+def test_large_planes_supported(lib, d):
+    st, n = ws_size(lib, Dims(*d))
+    assert st == 0, lib.nadmm_last_error()
+    assert n >= 17 * 4 * d[0] * d[1] * d[2]
+
+
 @pytest.mark.parametrize("d", [(128, 128, 7), (6, 4, 4), (128, 129, 96), (512, 16, 16),
-                               (32, 256, 96), (0, 8, 8), (-8, 8, 8), (4, 4, 2)])
+                               (32, 250, 96), (0, 8, 8), (-8, 8, 8), (4, 4, 2)])
 def test_unsupported_sizes(lib, d):
     st, _ = ws_size(lib, Dims(*d))
     assert st == 2, lib.nadmm_last_error()

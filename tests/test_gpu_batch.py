@@ -1,0 +1,54 @@
+"""GPU parity of the batched registration (nadmm_register_batch): every pair
+of a batch must come out bit for bit as from its own nadmm_register call
+(the batch only adds a grid dimension), at a one-pass and at a split-plane
+size; one pair is also checked against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2109_12688_amd import api as A
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    A._lib.load()
+    return A
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("d,b", [((32, 24, 16), 3), ((8, 144, 128), 2), ((64, 64, 64), 2)])
+def test_batch_equals_single_calls(api, d, b):
+    f = np.stack([synth.random_volume(d, seed=60 + i, smooth_kmax=3) for i in range(b)])
+    m = np.stack([synth.random_volume(d, seed=80 + i, smooth_kmax=3) for i in range(b)])
+    lam, theta, order, outer, iters = 0.01, 0.1, 2, 3, 6
+    res = api.register_batch(gpu(f), gpu(m), lam, theta, order, outer, iters)
+    for i in range(b):
+        one = api.register(gpu(f[i]), gpu(m[i]), lam, theta, order, outer, iters)
+        assert torch.equal(res["disp"][i], one["disp"]), i
+        assert torch.equal(res["warped"][i], one["warped"]), i
+
+
+def test_batch_pair_vs_oracle(api):
+    d = (32, 24, 16)
+    f = np.stack([synth.random_volume(d, seed=90 + i, smooth_kmax=3) for i in range(2)])
+    m = np.stack([synth.random_volume(d, seed=95 + i, smooth_kmax=3) for i in range(2)])
+    res = api.register_batch(gpu(f), gpu(m), 0.02, 0.1, 2, 2, 5)
+    torch.cuda.synchronize()
+    ref = O.register(f[1].astype(np.float64), m[1].astype(np.float64), 0.02, 0.1, 2, 2, 5)
+    assert np.abs(res["disp"][1].cpu().numpy() - ref.disp).max() < 1e-3
+    assert np.abs(res["warped"][1].cpu().numpy() - ref.warped).max() < 1e-4
+
+
+def test_batch_rejects_bad_batch(api):
+    from paper_2109_12688_amd import _lib
+    with pytest.raises(Exception):
+        api.workspace_batch((16, 8, 8), 0)

@@ -100,3 +100,55 @@ def test_full_size_fourier_solve_and_admm(api, pair):
     gw, gb, gv = api.admm(gpu(J32), gpu(r32), w["lam"], w["theta"], w["order"], 3)
     for g_, e_ in ((gw, res.w), (gb, res.b), (gv, res.v)):
         assert np.abs(host(g_) - e_).max() / np.abs(e_).max() < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# 192x192x128 phantom, images stored as bfloat16 (n = 3, lambda = 0.005,
+# 10 x 30), in the launch configuration bench.py times for it.  The y-z
+# planes (192 x 128) exceed one workgroup's LDS: pass B runs split.
+# ---------------------------------------------------------------------------
+NAME4 = "phantom192x192x128"
+
+
+@pytest.fixture(scope="module")
+def golden4():
+    with open(os.path.join(HERE, "golden", f"{NAME4}_oracle_samples.json")) as f:
+        return json.load(f)
+
+
+def test_bf16_full_registration_sampled(api, golden4):
+    w = synth.WORKLOADS[NAME4]
+    pair = synth.make_pair(NAME4)
+    fb, mb = synth.bf16_bits(pair.fixed), synth.bf16_bits(pair.moving)
+    h = hashlib.sha256()
+    h.update(fb.tobytes())
+    h.update(mb.tobytes())
+    assert h.hexdigest() == golden4["input_sha256"], "synthetic inputs drifted: rerun make_golden.py"
+    to_gpu = lambda b: torch.from_numpy(b.view(np.int16)).cuda().view(torch.bfloat16)  # noqa: E731
+    shp = pair.fixed.shape
+    ws = api.workspace(shp)
+    res = api.register(to_gpu(fb), to_gpu(mb), w["lam"], w["theta"], w["order"], w["outer"],
+                       w["iters"], ws=ws)
+    idx = np.array(golden4["indices"])
+    disp = host(res["disp"]).reshape(3, -1)[:, idx]
+    warped = host(res["warped"]).reshape(-1)[idx]
+    g = golden4["bf16"]
+    derr = np.abs(disp - np.array(g["disp"])).max()
+    werr = np.abs(warped - np.array(g["warped"])).max()
+    # against the oracle on the float32 images: what bfloat16 storage costs
+    f = golden4["fp32"]
+    dq = np.abs(disp - np.array(f["disp"]))
+    wq = np.abs(warped - np.array(f["warped"]))
+    stats, nneg, _ = api.jacobian(res["disp"], ws=ws)
+    s = host(stats)
+    print(f"bf16 192x192x128: vs oracle(bf16 images) disp {derr:.3e} warped {werr:.3e}; "
+          f"vs oracle(fp32 images) disp max {dq.max():.3e} mean {dq.mean():.3e}, warped max "
+          f"{wq.max():.3e} mean {wq.mean():.3e}; min det J {s[0]:.4f} (oracle bf16 "
+          f"{g['jacobian']['min']:.4f}, fp32 {f['jacobian']['min']:.4f})")
+    assert derr < 1e-3
+    assert werr < 1e-4
+    mn, mx, mean, cnt = O.jacobian_stats(host(res["disp"]))
+    assert abs(s[0] - mn) < 1e-12 and abs(s[1] - mx) < 1e-12 and abs(s[2] - mean) < 1e-12
+    assert int(nneg.cpu()[0]) == cnt
+    assert abs(mn - g["jacobian"]["min"]) < 1e-2
+    assert abs(cnt - g["jacobian"]["n_nonpos"]) <= g["jacobian"]["n_abs_below_1e-2"]

@@ -69,6 +69,33 @@ def test_fourier_solve(api, d, order):
     assert rel(host(w), ref) < 1e-5
 
 
+# y-z planes above 16384 points: pass B runs as three launches (rows,
+# columns, rows) instead of one plane per workgroup
+SPLIT_SHAPES = [(8, 144, 128), (12, 192, 96), (16, 96, 192)]
+
+
+@pytest.mark.parametrize("d", SPLIT_SHAPES)
+@pytest.mark.parametrize("order", [1, 3])
+def test_fourier_solve_split_planes(api, d, order):
+    s = synth.random_vector_field(d, seed=40 + order, amp=2.0)
+    lam, theta = 0.21, 0.13
+    w = api.fourier_solve(gpu(s), lam, theta, order)
+    ref = O.fourier_solve(f64(s), O.w_step_multiplier(d, lam, theta, order))
+    assert rel(host(w), ref) < 1e-5
+
+
+def test_admm_split_planes(api):
+    d = (12, 192, 96)
+    f = synth.random_volume(d, seed=44, smooth_kmax=3)
+    m = synth.random_volume(d, seed=45, smooth_kmax=3)
+    _, J, r = O.warp_grad_residual(f64(m), f64(f), np.zeros((3,) + f.shape))
+    J32, r32 = J.astype(np.float32), r.astype(np.float32)
+    res = O.admm(f64(J32), f64(r32), 0.005, 0.1, 3, 4)
+    gw, gb, gv = api.admm(gpu(J32), gpu(r32), 0.005, 0.1, 3, 4)
+    for g_, e_ in ((gw, res.w), (gb, res.b), (gv, res.v)):
+        assert rel(host(g_), e_) < 2e-5
+
+
 def test_fourier_solve_plane_wave_and_dc(api):
     d = (32, 24, 18)
     nx, ny, nz = d
