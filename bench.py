@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--workload", default="phantom128x128x96")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch of 32 uneven pairs (batched vs one-by-one)")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the bfloat16-image run at 192x192x128 (vs the float32 path)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -81,6 +83,8 @@ def copy_probe_bytes(V: int) -> int:
 def traffic_record(fetch_csv, write_csv, workload, kernel):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of `kernel`, each scaled by
     what the same counter reads for the copy probe of known size."""
+    import numpy as np
+
     def per_dispatch(path, counter):
         sums = {}
         for r in csv.DictReader(open(path)):
@@ -93,9 +97,10 @@ def traffic_record(fetch_csv, write_csv, workload, kernel):
                 continue
             d = sums.setdefault(key, {})
             d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
-        return {k: sum(v.values()) / len(v) for k, v in sums.items()}
+        # median over dispatches: the probe's copy kernel also serves a few
+        # small runtime copies, and a warping's first iteration reads less
+        return {k: float(np.median(list(v.values()))) for k, v in sums.items()}
 
-    import numpy as np
     import synth
     V = int(np.prod(synth.WORKLOADS[workload]["dims"]))
     cb = copy_probe_bytes(V)
@@ -152,14 +157,99 @@ def cpu_baseline(pair, w):
                       f"numpy float64 single thread, {dt:.2f} s"}
 
 
-def bf16_vs_plain(api, torch, synth, reps=3):
+def generate_inputs(args):
+    """Every input pair, made in a process pool (the generators are pure NumPy
+    on the host).  Runs before anything touches the GPU."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import synth
+
+    jobs = {"main": (synth.make_pair, args.workload)}
+    if not args.no_bf16:
+        jobs["bf16"] = (synth.make_pair, "phantom192x192x128")
+    if not args.no_batch:
+        for i, spec in enumerate(synth.batch_specs(32)):
+            jobs[("batch", i)] = (synth.batch_pair, spec)
+    workers = max(1, min(16, os.cpu_count() or 1, len(jobs)))
+    log(f"generating {len(jobs)} input pairs on {workers} processes")
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = {k: ex.submit(f, a) for k, (f, a) in jobs.items()}
+        out = {k: f.result() for k, f in futs.items()}
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+    return out
+
+
+def batch_vs_plain(api, torch, synth, pairs, reps=2):
+    """The 32 uneven pairs registered one call per pair, and batched: one
+    nadmm_register_batch call per size, the three sizes on separate streams.
+    Wall time of the whole set from HIP events on the launching stream."""
+    import numpy as np
+    w = synth.BATCH_PARAMS
+    specs = synth.batch_specs(32)
+    args = (w["lam"], w["theta"], w["order"], w["outer"], w["iters"])
+    single = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()) for f, m in pairs]
+    sizes = sorted({d for d, _ in specs})
+    ws1 = {d: api.workspace((d[2], d[1], d[0])) for d in sizes}
+    outs = [None] * len(specs)
+
+    def plain():
+        for i, ((f, m), (d, _)) in enumerate(zip(single, specs)):
+            outs[i] = api.register(f, m, *args, ws=ws1[d])
+
+    groups = {}
+    for i, (d, _) in enumerate(specs):
+        groups.setdefault(d, []).append(i)
+    stacked = {d: (torch.stack([single[i][0] for i in idx]), torch.stack([single[i][1] for i in idx]))
+               for d, idx in groups.items()}
+    wsb = {d: api.workspace_batch((d[2], d[1], d[0]), len(idx)) for d, idx in groups.items()}
+    streams = {d: torch.cuda.Stream() for d in groups}
+    bouts = {}
+
+    def batched():
+        cur = torch.cuda.current_stream()
+        for d in groups:
+            s = streams[d]
+            s.wait_stream(cur)
+            with torch.cuda.stream(s):
+                bouts[d] = api.register_batch(stacked[d][0], stacked[d][1], *args, ws=wsb[d])
+        for d in groups:
+            cur.wait_stream(streams[d])
+
+    def ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        cur = torch.cuda.current_stream()
+        e0.record(cur)
+        for _ in range(reps):
+            fn()
+        e1.record(cur)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_plain = ms(plain)
+    t_batch = ms(batched)
+    same = all(torch.equal(bouts[d]["disp"][j], outs[i]["disp"]) for d, idx in groups.items()
+               for j, i in enumerate(idx))
+    nvox = int(sum(np.prod(d) for d, _ in specs))
+    log(f"batch of {len(specs)}: one by one {t_plain:.2f} ms, batched {t_batch:.2f} ms")
+    return {"pairs": len(specs), "sizes": {"x".join(map(str, d)): len(idx) for d, idx in groups.items()},
+            "voxels": nvox, "outer": w["outer"], "iters": w["iters"], "steps": reps,
+            "ms_one_by_one": round(t_plain, 3), "ms_batched": round(t_batch, 3),
+            "pairs_per_s_one_by_one": round(1000.0 * len(specs) / t_plain, 2),
+            "pairs_per_s_batched": round(1000.0 * len(specs) / t_batch, 2),
+            "batched_vs_one_by_one": round(t_plain / t_batch, 4),
+            "bit_identical": bool(same)}
+
+
+def bf16_vs_plain(api, torch, synth, pair, reps=3):
     """The precision workload (192x192x128 phantom, n = 3, lambda = 0.005,
     10 x 30) registered from bfloat16 and from float32 images on the same
     GPU; ms per registration of each (event-timed, inputs resident)."""
     name = "phantom192x192x128"
     w = synth.WORKLOADS[name]
-    log(f"generating {name}")
-    pair = synth.make_pair(name)
     shp = pair.fixed.shape
     ws = api.workspace(shp)
     f32 = (torch.from_numpy(pair.fixed).cuda(), torch.from_numpy(pair.moving).cuda())
@@ -205,6 +295,8 @@ def main():
               "part of this build", file=sys.stderr)
         sys.exit(2)
     import numpy as np
+
+    inputs = generate_inputs(args)  # before any GPU use
     import torch
 
     import synth
@@ -215,8 +307,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     w = synth.WORKLOADS[args.workload]
-    log(f"generating {args.workload}")
-    pair = synth.make_pair(args.workload)
+    pair = inputs["main"]
     fixed = torch.from_numpy(pair.fixed).cuda()
     moving = torch.from_numpy(pair.moving).cuda()
     shp = tuple(fixed.shape)
@@ -321,7 +412,10 @@ def main():
         "n_det_nonpos": int(nneg.item()),
     }
     if not args.no_bf16:
-        res["bf16"] = bf16_vs_plain(api, torch, synth)
+        res["bf16"] = bf16_vs_plain(api, torch, synth, inputs["bf16"])
+    if not args.no_batch:
+        res["batch"] = batch_vs_plain(api, torch, synth,
+                                      [inputs[("batch", i)] for i in range(32)])
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the CPU")
         res["cpu_baseline"] = cpu_baseline(pair, w)

@@ -265,6 +265,26 @@ WORKLOADS = {
 }
 
 
+# Batch of uneven phantom pairs: pair i has seed 1000 + i and a size drawn
+# uniformly from BATCH_SIZES by a seed-999 generator; phantom geometry scales
+# with the volume, largest displacement 8 voxels.
+BATCH_SIZES = ((64, 64, 64), (96, 96, 64), (128, 128, 96))
+BATCH_PARAMS = dict(lam=0.01, theta=0.1, order=2, outer=10, iters=20, max_disp=8.0)
+
+
+def batch_specs(n: int = 32):
+    """[(dims_xyz, seed)] of the n pairs of the batch workload."""
+    pick = np.random.default_rng(999).integers(0, len(BATCH_SIZES), size=n)
+    return [(BATCH_SIZES[int(k)], 1000 + i) for i, k in enumerate(pick)]
+
+
+def batch_pair(spec) -> tuple:
+    """(fixed, moving) of one batch pair (spec from batch_specs)."""
+    dims, seed = spec
+    p = phantom_pair(dims, seed, BATCH_PARAMS["max_disp"])
+    return p.fixed, p.moving
+
+
 def _cache_dir():
     import os
     d = os.environ.get("NADMM_SYNTH_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "nadmm_synth"))
