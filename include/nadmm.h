@@ -141,6 +141,26 @@ nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_param
                                   const float* init_disp, float* disp, float* warped,
                                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* Gradient of one warping's image match (the differentiated hot path):
+ *   L = sum_x (I1(x + w(x)) - I0(x))^2,
+ * with w the velocity of ONE warping from u = 0 (Sec. 2): `p->iters`
+ * iterations of Eq. (5) with the L2 data step of Eq. (6) for J = grad I1,
+ * r = I1 - I0 (p->outer is ignored; data_term must be 2).  Writes the loss
+ * and dL/dlambda to device doubles *loss and *d_lambda, and dL/dI1 to the
+ * device scalar volume d_moving, by reverse-mode differentiation through
+ * the unrolled iterations (the Fourier solve is self-adjoint; its lambda
+ * derivative is the multiplier -theta K^n / (theta + lambda K^n)^2).  The
+ * iteration states are stored every `checkpoint` (1..30) iterations and
+ * recomputed in between.  The image adjoint of the final warp is a
+ * scatter-add with float atomics, so d_moving may differ in the last bits
+ * between runs.  Workspace: nadmm_workspace_size_grad bytes. */
+nadmm_status nadmm_workspace_size_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpoint,
+                                       size_t* bytes);
+nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpoint,
+                            const float* fixed, const float* moving, double* loss,
+                            float* d_moving, double* d_lambda, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
 /* One ADMM solve (Eq. (5), (6)) for a given linearised data term:
  * `p->iters` iterations from zero with J = grad I1^w (vector field) and
  * r = I1^w - I0 (scalar volume).  Writes the final iterates w (vector

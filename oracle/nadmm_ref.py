@@ -318,3 +318,157 @@ def jacobian_stats(disp: np.ndarray):
 
 def ssd(a: np.ndarray, b: np.ndarray) -> float:
     return float(np.sum((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Differentiation of one warping (reverse mode through Sec. 3, Eq. (5), (6))
+# ---------------------------------------------------------------------------
+# The loss is the SSD between the fixed image and the moving image warped by
+# the velocity of ONE warping from u = 0 (Sec. 2, the first pass of the
+# iterative scheme), i.e. L = sum (I1(x + w(x)) - I0(x))^2 with w the final
+# ADMM iterate of Eq. (5) for J = grad I1, r = I1 - I0.  The gradients with
+# respect to I1 and lambda are taken by reverse-mode differentiation of the
+# recurrence exactly as `admm` runs it, each step's adjoint written out:
+#   a = w_hat - b_hat;  v = D(a);  s = v + b_hat;  w = S s;  b = s - w;
+#   w_hat' = w + gamma (w - w_prev);  b_hat' = b + gamma (b - b_prev).
+# S is real-symmetric in the Fourier basis (S^T = S) and
+# dS/dlambda = F^-1 [ -theta K^n / (theta + lambda K^n)^2 ] F.
+
+def trilinear_transpose(g: np.ndarray, disp: np.ndarray) -> np.ndarray:
+    """W^T g for the warp W f = trilinear_periodic(f, disp): each voxel's
+    value g(x) is added to the 8 grid points around x + disp(x) with the
+    trilinear weights (so <W f, g> = <f, W^T g>)."""
+    nz, ny, nx = disp.shape[1:]
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    px, py, pz = xx + disp[0], yy + disp[1], zz + disp[2]
+    fx, fy, fz = np.floor(px), np.floor(py), np.floor(pz)
+    tx, ty, tz = px - fx, py - fy, pz - fz
+    ix0 = np.mod(fx.astype(np.int64), nx)
+    iy0 = np.mod(fy.astype(np.int64), ny)
+    iz0 = np.mod(fz.astype(np.int64), nz)
+    out = np.zeros((nz, ny, nx))
+    for dz, wz in ((0, 1 - tz), (1, tz)):
+        for dy, wy in ((0, 1 - ty), (1, ty)):
+            for dx, wx in ((0, 1 - tx), (1, tx)):
+                np.add.at(out, (np.mod(iz0 + dz, nz), np.mod(iy0 + dy, ny), np.mod(ix0 + dx, nx)),
+                          wz * wy * wx * g)
+    return out
+
+
+def trilinear_position_gradient(f: np.ndarray, disp: np.ndarray) -> np.ndarray:
+    """d/dp of the trilinear interpolant of f at p = x + disp(x), per axis
+    (the one-sided derivative at integer positions, where the floor is
+    taken): shape (3, nz, ny, nx)."""
+    nz, ny, nx = disp.shape[1:]
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    px, py, pz = xx + disp[0], yy + disp[1], zz + disp[2]
+    fx, fy, fz = np.floor(px), np.floor(py), np.floor(pz)
+    tx, ty, tz = px - fx, py - fy, pz - fz
+    x0 = np.mod(fx.astype(np.int64), nx)
+    y0 = np.mod(fy.astype(np.int64), ny)
+    z0 = np.mod(fz.astype(np.int64), nz)
+    x1, y1, z1 = np.mod(x0 + 1, nx), np.mod(y0 + 1, ny), np.mod(z0 + 1, nz)
+    c = {(i, j, k): f[(z0, z1)[k], (y0, y1)[j], (x0, x1)[i]]
+         for i in (0, 1) for j in (0, 1) for k in (0, 1)}
+    gx = ((1 - ty) * (1 - tz) * (c[1, 0, 0] - c[0, 0, 0]) + ty * (1 - tz) * (c[1, 1, 0] - c[0, 1, 0])
+          + (1 - ty) * tz * (c[1, 0, 1] - c[0, 0, 1]) + ty * tz * (c[1, 1, 1] - c[0, 1, 1]))
+    gy = ((1 - tx) * (1 - tz) * (c[0, 1, 0] - c[0, 0, 0]) + tx * (1 - tz) * (c[1, 1, 0] - c[1, 0, 0])
+          + (1 - tx) * tz * (c[0, 1, 1] - c[0, 0, 1]) + tx * tz * (c[1, 1, 1] - c[1, 0, 1]))
+    gz = ((1 - tx) * (1 - ty) * (c[0, 0, 1] - c[0, 0, 0]) + tx * (1 - ty) * (c[1, 0, 1] - c[1, 0, 0])
+          + (1 - tx) * ty * (c[0, 1, 1] - c[0, 1, 0]) + tx * ty * (c[1, 1, 1] - c[1, 1, 0]))
+    return np.stack([gx, gy, gz])
+
+
+def v_step_l2_adjoint(gv: np.ndarray, a: np.ndarray, J: np.ndarray, r: np.ndarray,
+                      theta: float):
+    """Transpose of the Jacobian of v = a - J (J.a + r) / (theta + |J|^2)
+    applied to gv: returns (ga, gJ, gr).  With q = theta + |J|^2 and
+    f = (J.a + r) / q:  dv/da = I - J J^T / q (symmetric),  dv/dr = -J / q,
+    dv_i/dJ_j = -delta_ij f - J_i (a_j - 2 f J_j) / q."""
+    q = theta + np.sum(J * J, axis=0)
+    f = (np.sum(J * a, axis=0) + r) / q
+    jg = np.sum(J * gv, axis=0)
+    ga = gv - J * (jg / q)[None]
+    gr = -jg / q
+    gJ = -f[None] * gv - (jg / q)[None] * (a - 2.0 * f[None] * J)
+    return ga, gJ, gr
+
+
+def ssd_one_warping(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float,
+                    order: int, iters: int) -> float:
+    """L = sum (I1(x + w(x)) - I0(x))^2 with w the velocity of one warping."""
+    _, J, r = warp_grad_residual(moving, fixed, np.zeros((3,) + fixed.shape))
+    w = admm(J, r, lam, theta, order, iters).w
+    return ssd(trilinear_periodic(moving, w), fixed)
+
+
+def ssd_one_warping_grad(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float,
+                         order: int, iters: int):
+    """(L, dL/dI1, dL/dlambda) of `ssd_one_warping` (L2 data term), by
+    reverse-mode differentiation of the recurrence of `admm`."""
+    fixed = np.asarray(fixed, np.float64)
+    moving = np.asarray(moving, np.float64)
+    dims_xyz = (fixed.shape[2], fixed.shape[1], fixed.shape[0])
+    zero_u = np.zeros((3,) + fixed.shape)
+    iw, J, r = warp_grad_residual(moving, fixed, zero_u)  # iw == moving exactly at u = 0
+    mult = w_step_multiplier(dims_xyz, lam, theta, order)
+    kn = laplacian_symbol(dims_xyz) ** order
+    dmult = -theta * kn / (theta + lam * kn) ** 2  # d mult / d lambda
+    # forward, keeping what the adjoint needs
+    zeros = np.zeros_like(J)
+    w_hat, b_hat, w_prev, b_prev = zeros, zeros, zeros, zeros
+    alpha = 1.0
+    tape = []
+    for _ in range(iters):
+        a = w_hat - b_hat
+        v = v_step_l2(a, J, r, theta)
+        s = v + b_hat
+        w = fourier_solve(s, mult)
+        b = s - w
+        alpha_next = (1.0 + math.sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0
+        g = (alpha - 1.0) / alpha_next
+        tape.append((a, s, g))
+        w_hat = w + g * (w - w_prev)
+        b_hat = b + g * (b - b_prev)
+        w_prev, b_prev = w, b
+        alpha = alpha_next
+    warped = trilinear_periodic(moving, w)
+    resid = warped - fixed
+    loss = float(np.sum(resid * resid))
+    gwarp = 2.0 * resid
+    d_moving = trilinear_transpose(gwarp, w)
+    # adjoints of w^k and b^k, accumulated as later iterations are reversed
+    gw = {iters - 1: gwarp[None] * trilinear_position_gradient(moving, w)}
+    gb = {}
+    gJ = np.zeros_like(J)
+    gr = np.zeros_like(r)
+    d_lam = 0.0
+    for k in range(iters - 1, -1, -1):
+        a, s, _ = tape[k]
+        gwk = gw.pop(k, zeros)
+        gbk = gb.pop(k, zeros)
+        # b = s - w, w = S s
+        gw_tot = gwk - gbk
+        gs = gbk + fourier_solve(gw_tot, mult)
+        d_lam += float(np.sum(gw_tot * fourier_solve(s, dmult)))
+        # s = v + b_hat, v = D(a), a = w_hat - b_hat
+        ga, gJk, grk = v_step_l2_adjoint(gs, a, J, r, theta)
+        gJ += gJk
+        gr += grk
+        g_what = ga
+        g_bhat = gs - ga
+        if k >= 1:
+            # w_hat^k = w^{k-1} + gamma_{k-1} (w^{k-1} - w^{k-2}) (and b likewise)
+            gam = tape[k - 1][2]
+            gw[k - 1] = gw.get(k - 1, zeros) + (1.0 + gam) * g_what
+            gb[k - 1] = gb.get(k - 1, zeros) + (1.0 + gam) * g_bhat
+            if k >= 2:
+                gw[k - 2] = gw.get(k - 2, zeros) - gam * g_what
+                gb[k - 2] = gb.get(k - 2, zeros) - gam * g_bhat
+    # J = grad I1 (central differences: the transpose is minus the same
+    # difference), r = I1 - I0, and I1^w = I1 at u = 0
+    d_iw = gr.copy()
+    for c, ax in enumerate(AXIS_OF_COMPONENT):
+        d_iw -= central_diff(gJ[c], ax)
+    d_moving += d_iw
+    return loss, d_moving, d_lam

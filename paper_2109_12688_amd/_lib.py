@@ -47,6 +47,10 @@ _SIGS = {
     "nadmm_workspace_size_batch": ([Dims, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "nadmm_register_batch": ([Dims, ctypes.c_int32, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P,
                               ctypes.c_size_t, _P], ctypes.c_int),
+    "nadmm_workspace_size_grad": ([Dims, ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+                                  ctypes.c_int),
+    "nadmm_ssd_grad": ([Dims, ctypes.POINTER(Params), ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
+                       ctypes.c_int),
     "nadmm_admm": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_fourier_solve": ([Dims, ctypes.POINTER(Params), _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_warp": ([Dims, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),

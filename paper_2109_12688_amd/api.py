@@ -144,6 +144,36 @@ def register_batch(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta:
     return {"disp": disp, "warped": warped}
 
 
+def workspace_grad(vol_shape, lam: float, theta: float, order: int, iters: int, checkpoint: int,
+                   device="cuda") -> torch.Tensor:
+    n = ctypes.c_size_t(0)
+    p = params(lam, theta, order, 1, iters)
+    _lib.call("nadmm_workspace_size_grad", dims_of(vol_shape), ctypes.byref(p), ctypes.c_int32(checkpoint),
+              ctypes.byref(n))
+    return torch.empty(int(n.value), dtype=torch.uint8, device=device)
+
+
+def ssd_grad(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
+             iters: int, checkpoint: int = 5, ws: torch.Tensor | None = None):
+    """Loss, dL/dmoving and dL/dlambda of one warping's image match
+    L = sum (moving(x + w(x)) - fixed(x))^2 (see nadmm_ssd_grad).  Returns
+    (loss, d_moving, d_lambda) with loss and d_lambda float64 0-d tensors."""
+    _check(fixed, "fixed")
+    shp = tuple(fixed.shape)
+    _check(moving, "moving", shp)
+    if ws is None:
+        ws = workspace_grad(shp, lam, theta, order, iters, checkpoint, fixed.device)
+    _check(ws, "workspace", dtype=torch.uint8)
+    loss = torch.empty((), dtype=torch.float64, device=fixed.device)
+    dlam = torch.empty((), dtype=torch.float64, device=fixed.device)
+    dmov = torch.empty_like(moving)
+    p = params(lam, theta, order, 1, iters)
+    _lib.call("nadmm_ssd_grad", dims_of(shp), ctypes.byref(p), ctypes.c_int32(checkpoint), _ptr(fixed),
+              _ptr(moving), _ptr(loss), _ptr(dmov), _ptr(dlam), _ptr(ws), ctypes.c_size_t(ws.numel()),
+              _stream())
+    return loss, dmov, dlam
+
+
 def admm(J: torch.Tensor, r: torch.Tensor, lam: float, theta: float, order: int, iters: int,
          data_term: int = 2, eps: float = 1e-8, ws: torch.Tensor | None = None):
     """``iters`` ADMM iterations from zero for a given J, r.  Returns (w, b, v)."""

@@ -201,14 +201,26 @@ Plans plans(const nadmm_dims& d) { return Plans{make_plan(d.nx), make_plan(d.ny)
 // through passes A and B; pass C (with its mode) is issued by the caller.
 hipError_t spectral_ab(const Geo& g, const Plans& pl, const Tables& tb, const nadmm_params* p,
                        const float* s1, const float* s2, float gamma, float2* X, hipStream_t st,
-                       int batch = 1) {
+                       int batch = 1, bool deriv = false) {
   hipError_t e = timed(KK_PASS_A, st, [&] {
     return launch_pass_a(g, pl.x, tb, s1, s2, gamma, X, st, batch);
   });
   if (e != hipSuccess) return e;
   return timed(KK_PASS_B, st, [&] {
-    return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch);
+    return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch, deriv);
   });
+}
+
+// out = S t (or (dS/dlambda) t) for t = s1 + gamma (s1 - s2), one field.
+hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const nadmm_params* p,
+                          const float* s1, const float* s2, float gamma, float2* X, float* out,
+                          hipStream_t st, bool deriv = false) {
+  hipError_t e = spectral_ab(g, pl, tb, p, s1, s2, gamma, X, st, 1, deriv);
+  if (e != hipSuccess) return e;
+  PassCArgs a{};
+  a.X = X;
+  a.out = out;
+  return timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c(g, pl.x, tb, kOutY, a, st); });
 }
 
 // The ADMM loop of one warping in the two-field form, with s^0 already in
@@ -322,6 +334,56 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
   return NADMM_OK;
 }
 
+// ---- differentiated warping ---------------------------------------------
+// Workspace of nadmm_ssd_grad: J, r, the spectrum and tables as for a
+// registration, then the iteration states (checkpoint pairs and a segment
+// buffer), the adjoint ring and temporaries, all float32 vector fields.
+struct GradLayout {
+  int nseg, nbuf;
+  size_t J, r, gr, resid, X, tab, part, f3[64];
+  int nf3;
+  size_t total;
+};
+
+int grad_segments(int iters, int c) { return iters <= 1 ? 0 : (iters - 1 + c - 1) / c; }
+
+GradLayout grad_layout(const nadmm_dims& d, int iters, int c) {
+  const size_t V = (size_t)d.nx * d.ny * d.nz;
+  const size_t f3 = align256(3 * V * sizeof(float)), f1 = align256(V * sizeof(float));
+  GradLayout L{};
+  L.nseg = grad_segments(iters, c);
+  L.nbuf = c - 1 > 2 ? c - 1 : 2;
+  // checkpoints (2 per segment), shared segment/rolling buffers, ring (3),
+  // y, gy, gt, tmp, w, gw, gJ
+  L.nf3 = 2 * (L.nseg > 0 ? L.nseg : 1) + L.nbuf + 3 + 7;
+  size_t o = 0;
+  L.J = o; o += f3;
+  L.r = o; o += f1;
+  L.gr = o; o += f1;
+  L.resid = o; o += f1;
+  L.X = o; o += align256((size_t)3 * (d.nx / 2 + 1) * d.ny * d.nz * 2 * sizeof(float));
+  L.tab = o; o += align256(tables_bytes(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}));
+  L.part = o; o += align256(dot_partials() * sizeof(double));
+  for (int i = 0; i < L.nf3; ++i) {
+    L.f3[i] = o;
+    o += f3;
+  }
+  L.total = o;
+  return L;
+}
+
+nadmm_status check_grad_args(const nadmm_params* p, int32_t checkpoint) {
+  CHECK(check_params(p, false));
+  if (p->data_term != 2)
+    return fail(NADMM_ERR_INVALID_ARG, "the gradient supports the L2 data term (data_term 2) only");
+  if (p->iters > 100000) return fail(NADMM_ERR_INVALID_ARG, "iters too large");
+  if (checkpoint < 1 || checkpoint > 30)
+    return fail(NADMM_ERR_INVALID_ARG, "checkpoint must be in [1, 30] (got %d)", checkpoint);
+  if (2 * grad_segments(p->iters, checkpoint) + 12 + (checkpoint > 3 ? checkpoint - 1 : 2) > 64)
+    return fail(NADMM_ERR_INVALID_ARG, "iters / checkpoint needs too many stored states");
+  return NADMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -380,6 +442,130 @@ nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_param
   CHECK(check_batch(batch));
   return register_impl(d, p, fixed, moving, init_disp, disp, warped, nullptr, workspace,
                        workspace_bytes, stream, batch);
+}
+
+nadmm_status nadmm_workspace_size_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpoint,
+                                       size_t* bytes) {
+  if (!bytes) return fail(NADMM_ERR_INVALID_ARG, "bytes is NULL");
+  CHECK(check_dims(d));
+  CHECK(check_grad_args(p, checkpoint));
+  *bytes = grad_layout(d, p->iters, checkpoint).total;
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpoint,
+                            const float* fixed, const float* moving, double* loss,
+                            float* d_moving, double* d_lambda, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_grad_args(p, checkpoint));
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(d_moving, "d_moving", false));
+  if (!loss || !d_lambda) return fail(NADMM_ERR_INVALID_ARG, "loss and d_lambda must not be NULL");
+  CHECK(check_ptr(workspace, "workspace", false));
+  const GradLayout L = grad_layout(d, p->iters, checkpoint);
+  if (workspace_bytes < L.total)
+    return fail(NADMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                workspace_bytes, L.total);
+  const Geo g = geo(d);
+  const Plans pl = plans(d);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t V = (size_t)g.V;
+  const int K = p->iters, c = checkpoint;
+  const float theta = (float)p->theta;
+  float* J = at<float>(workspace, L.J);
+  float* r = at<float>(workspace, L.r);
+  float* gr = at<float>(workspace, L.gr);
+  float* resid = at<float>(workspace, L.resid);
+  float2* X = at<float2>(workspace, L.X);
+  double* part = at<double>(workspace, L.part);
+  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
+  int f = 0;
+  auto field = [&]() { return at<float>(workspace, L.f3[f++]); };
+  const int nck = L.nseg > 0 ? L.nseg : 1;
+  std::vector<float*> ck_prev(nck), ck_cur(nck), buf(L.nbuf);
+  for (int j = 0; j < nck; ++j) {
+    ck_prev[j] = field();
+    ck_cur[j] = field();
+  }
+  for (int i = 0; i < L.nbuf; ++i) buf[i] = field();
+  float* ring[3] = {field(), field(), field()};
+  float* y = field();
+  float* gy = field();
+  float* gt = field();
+  float* tmp = field();
+  float* w = field();
+  float* gw = field();
+  float* gJ = field();
+  const std::vector<double> gam = nesterov_gammas(K);
+  HIP_TRY(launch_tables(g, tb, st));
+
+  // forward: s^k goes to checkpoint j's slots for k = j c (and j c - 1),
+  // otherwise to one of two rolling buffers (in place over s^{k-2})
+  auto fwd_slot = [&](int k) -> float* {
+    if (k % c == 0 && k / c < nck) return ck_cur[k / c];
+    if ((k + 1) % c == 0 && (k + 1) / c < nck && k + 1 > 0) return ck_prev[(k + 1) / c];
+    return buf[k % 2];
+  };
+  // u = 0: the warped source is the moving image itself
+  HIP_TRY(launch_grad_resid(g, moving, fixed, J, r, fwd_slot(0), theta, (float)p->eps, 2, st));
+  for (int k = 1; k < K; ++k) {
+    const float* s1 = fwd_slot(k - 1);
+    const float* s2 = k >= 2 ? fwd_slot(k - 2) : nullptr;
+    const float gk = (float)gam[k - 1];
+    HIP_TRY(spectral_apply(g, pl, tb, p, s1, s2, gk, X, y, st));
+    HIP_TRY(launch_step_fwd(g, J, r, s1, s2, gk, y, fwd_slot(k), theta, st));
+  }
+  float* s_last = fwd_slot(K - 1);
+  HIP_TRY(spectral_apply(g, pl, tb, p, s_last, nullptr, 0.0f, X, w, st));
+
+  // loss, the image adjoint of the final warp, dL/dw
+  HIP_TRY(launch_fill(d_moving, 0.0f, V, st));
+  HIP_TRY(launch_warp_adjoint(g, moving, fixed, w, resid, d_moving, gw, st));
+  HIP_TRY(launch_dot(V, resid, resid, 1.0, false, part, loss, st));
+  // w = S s^{K-1}: dL/dlambda gets <gw, (dS/dlambda) s^{K-1}>, dL/ds^{K-1} = S gw
+  HIP_TRY(spectral_apply(g, pl, tb, p, s_last, nullptr, 0.0f, X, tmp, st, true));
+  HIP_TRY(launch_dot(3 * V, gw, tmp, 1.0, false, part, d_lambda, st));
+  for (int i = 0; i < 3; ++i) HIP_TRY(launch_fill(ring[i], 0.0f, 3 * V, st));
+  HIP_TRY(spectral_apply(g, pl, tb, p, gw, nullptr, 0.0f, X, ring[(K - 1) % 3], st));
+  HIP_TRY(launch_fill(gJ, 0.0f, 3 * V, st));
+  HIP_TRY(launch_fill(gr, 0.0f, V, st));
+
+  // backward, one segment of steps (b, kmax] at a time, newest first
+  for (int j = L.nseg - 1; j >= 0; --j) {
+    const int b = j * c, kmax = (b + c < K - 1) ? b + c : K - 1;
+    auto state = [&](int k) -> float* {
+      if (k < 0) return nullptr;
+      if (k == b) return ck_cur[j];
+      if (k == b - 1) return c == 1 ? ck_cur[j - 1] : ck_prev[j];  // c = 1 keeps every state
+      return buf[k - b - 1];
+    };
+    for (int k = b + 1; k <= kmax - 1; ++k) {  // recompute the segment's states
+      const float gk = (float)gam[k - 1];
+      HIP_TRY(spectral_apply(g, pl, tb, p, state(k - 1), state(k - 2), gk, X, y, st));
+      HIP_TRY(launch_step_fwd(g, J, r, state(k - 1), state(k - 2), gk, y, state(k), theta, st));
+    }
+    for (int k = kmax; k > b; --k) {
+      const float* s1 = state(k - 1);
+      const float* s2 = k >= 2 ? state(k - 2) : nullptr;
+      const float gk = (float)gam[k - 1];
+      float* gk_ = ring[k % 3];
+      HIP_TRY(spectral_apply(g, pl, tb, p, s1, s2, gk, X, y, st));
+      HIP_TRY(launch_adj_step(g, gk_, s1, s2, gk, y, J, r, theta, gy, gt, gJ, gr, st));
+      HIP_TRY(spectral_apply(g, pl, tb, p, gy, nullptr, 0.0f, X, tmp, st));
+      HIP_TRY(launch_adj_combine(3 * V, gt, tmp, gk, ring[(k - 1) % 3],
+                                 k >= 2 ? ring[(k - 2) % 3] : nullptr, st));
+      HIP_TRY(spectral_apply(g, pl, tb, p, s1, s2, gk, X, tmp, st, true));
+      HIP_TRY(launch_dot(3 * V, gy, tmp, 1.0, true, part, d_lambda, st));
+      HIP_TRY(launch_fill(gk_, 0.0f, 3 * V, st));  // becomes the adjoint of s^{k-3}
+    }
+  }
+  // s^0 = D(0; J, r)
+  HIP_TRY(launch_adj_step(g, ring[0], nullptr, nullptr, 0.0f, nullptr, J, r, theta, nullptr,
+                          nullptr, gJ, gr, st));
+  HIP_TRY(launch_grad_transpose(g, gJ, gr, d_moving, st));
+  return NADMM_OK;
 }
 
 nadmm_status nadmm_admm(nadmm_dims d, const nadmm_params* p, const float* J, const float* r,

@@ -460,14 +460,14 @@ constexpr bool team_search(int n, int m, int L, int depth, int* out) {
   return false;
 }
 
-constexpr TeamPlan make_team_plan_ce(int n, int max_lanes) {
+constexpr TeamPlan make_team_plan_ce(int n, int max_lanes, int min_lanes = 1) {
   TeamPlan best{};
   best.n = n;
   best.nstages = -1;
   const int Ls[5] = {16, 8, 4, 2, 1};
   for (int li = 0; li < 5; ++li) {
     const int L = Ls[li];
-    if (L > max_lanes || n % L || n / L > kTeamEpt) continue;
+    if (L > max_lanes || L < min_lanes || n % L || n / L > kTeamEpt) continue;
     int rad[4] = {0, 0, 0, 0};
     for (int depth = 1; depth <= 4; ++depth) {
       if (team_search(n, n, L, depth, rad)) {
@@ -612,16 +612,19 @@ __device__ __forceinline__ void team_fft(float2* buf, const float2* tw, const Te
 // registers: forward butterfly j of the last stage produces elements
 // j + r N/R, exactly the inputs of inverse butterfly j of the first stage.
 // The multiplier of spectral element e of this line is
-// theta / (theta + lambda (kq + ks[e])^order) * scale.
+// theta / (theta + lambda (kq + ks[e])^order) * scale (or its derivative
+// with respect to lambda).
 struct SpectralMult {
   const float* ks;
   float kq, lambda, theta, scale;
   int order;
+  int deriv;  // nonzero: d/dlambda of the multiplier, -theta K^n / (theta + lambda K^n)^2
   __device__ __forceinline__ float operator()(int e) const {
     const float k0 = kq + ks[e];
     float kn = k0;
     for (int i = 1; i < order; ++i) kn *= k0;
-    return theta * scale * __builtin_amdgcn_rcpf(theta + lambda * kn);
+    const float rd = __builtin_amdgcn_rcpf(theta + lambda * kn);
+    return deriv ? -theta * scale * kn * rd * rd : theta * scale * rd;
   }
 };
 

@@ -117,11 +117,33 @@ hipError_t launch_admm_init(const Geo& g, const float* J, const float* r, float*
                             float theta, float eps, int data_term, hipStream_t st);
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
                          const float* s2, float gamma, float2* X, hipStream_t st, int batch = 1);
+// deriv: multiply by d/dlambda of the w-step multiplier instead of the multiplier.
 hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
-                         int order, hipStream_t st, int batch = 1);
+                         int order, hipStream_t st, int batch = 1, bool deriv = false);
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
                          const PassCArgs& a, hipStream_t st, int batch = 1);
 hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out, hipStream_t st);
+
+// Differentiated warping (adjoint.hip).  Fields are float32 vector fields
+// (3V) unless noted; r, gr, resid, d_img are scalar volumes.
+hipError_t launch_step_fwd(const Geo& g, const float* J, const float* r, const float* s1,
+                           const float* s2, float gamma, const float* y, float* s_out, float theta,
+                           hipStream_t st);
+hipError_t launch_adj_step(const Geo& g, const float* gs, const float* s1, const float* s2,
+                           float gamma, const float* y, const float* J, const float* r,
+                           float theta, float* gy, float* gt, float* gJ, float* gr,
+                           hipStream_t st);
+hipError_t launch_adj_combine(size_t n, const float* gt_pre, const float* sgy, float gamma,
+                              float* g1, float* g2, hipStream_t st);
+hipError_t launch_warp_adjoint(const Geo& g, const float* img, const float* ref, const float* w,
+                               float* resid, float* d_img, float* gw, hipStream_t st);
+hipError_t launch_grad_transpose(const Geo& g, const float* gJ, const float* gr, float* d_img,
+                                 hipStream_t st);
+// *out (device double) = (accumulate ? *out : 0) + scale * sum a[i] b[i],
+// float64, fixed summation order; `partial` holds dot_partials() doubles.
+size_t dot_partials();
+hipError_t launch_dot(size_t n, const float* a, const float* b, double scale, bool accumulate,
+                      double* partial, double* out, hipStream_t st);
 hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* partial,
                            double* stats, int64_t* n_nonpos, hipStream_t st);
 

@@ -29,6 +29,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "pointwise.h"
 
 // Layout of the x-line buffers of passes A and C: butterflies of one line on
 // consecutive threads (XL_LINE_FAST 0) and one padding slot every
@@ -161,7 +162,15 @@ static int lane_budget(int nlines) {
   return b < 1 ? 1 : b;
 }
 TeamPlan plane_plan_y(const Geo& g) { return make_team_plan(g.ny, lane_budget(g.nz)); }
-TeamPlan plane_plan_z(const Geo& g) { return make_team_plan(g.nz, lane_budget(g.ny)); }
+// Smallest team for the z lines (a tuning knob: larger teams put more
+// wavefronts on the columns at the cost of more stages).
+#ifndef PLANE_Z_MIN_LANES
+#define PLANE_Z_MIN_LANES 1
+#endif
+TeamPlan plane_plan_z(const Geo& g) {
+  TeamPlan p = make_team_plan_ce(g.nz, lane_budget(g.ny), PLANE_Z_MIN_LANES);
+  return p.nstages > 0 ? p : make_team_plan(g.nz, lane_budget(g.ny));
+}
 
 static int plane_team_threads(const Geo& g) {
   const TeamPlan py = plane_plan_y(g), pz = plane_plan_z(g);
@@ -206,99 +215,6 @@ XDivs make_xdivs(const Geo& g) {
   d.ny = make_fastdiv(g.ny);
   d.nz = make_fastdiv(g.nz);
   return d;
-}
-
-// ---------------------------------------------------------------------------
-// periodic trilinear sampling
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int wrap_index(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
-}
-
-// Grid voxel x plus displacement u, split exactly into the integer cell
-// (taken modulo n) and the fraction: floor(x + u) = x + floor(u) and
-// frac(x + u) = u - floor(u) since x is an integer.  Non-finite u gives a
-// valid cell and a NaN fraction, never an out-of-range index.
-__device__ __forceinline__ void cell(int x, float u, int n, int& i0, int& i1, float& t) {
-  const float fu = floorf(u);
-  t = u - fu;
-  const float cl = fminf(fmaxf(fu, -1.0e9f), 1.0e9f);
-  i0 = wrap_index(x + (int)cl, n);
-  i1 = (i0 + 1 == n) ? 0 : i0 + 1;
-}
-
-__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
-
-struct Tap {
-  int o000, o100, o010, o110, o001, o101, o011, o111;
-  float tx, ty, tz;
-};
-
-__device__ __forceinline__ Tap make_tap(int x, int y, int z, float ux, float uy, float uz,
-                                        const Geo& g) {
-  int x0, x1, y0, y1, z0, z1;
-  Tap t;
-  cell(x, ux, g.nx, x0, x1, t.tx);
-  cell(y, uy, g.ny, y0, y1, t.ty);
-  cell(z, uz, g.nz, z0, z1, t.tz);
-  const int r00 = (z0 * g.ny + y0) * g.nx, r01 = (z0 * g.ny + y1) * g.nx;
-  const int r10 = (z1 * g.ny + y0) * g.nx, r11 = (z1 * g.ny + y1) * g.nx;
-  t.o000 = r00 + x0; t.o100 = r00 + x1;
-  t.o010 = r01 + x0; t.o110 = r01 + x1;
-  t.o001 = r10 + x0; t.o101 = r10 + x1;
-  t.o011 = r11 + x0; t.o111 = r11 + x1;
-  return t;
-}
-
-// Image element as float32: bfloat16 is the upper half of a float32.
-__device__ __forceinline__ float img_at(const float* __restrict__ f, int i) { return f[i]; }
-__device__ __forceinline__ float img_at(const uint16_t* __restrict__ f, int i) {
-  return __uint_as_float((uint32_t)f[i] << 16);
-}
-
-template <typename T>
-__device__ __forceinline__ float sample(const T* __restrict__ f, const Tap& t) {
-  const float c00 = lerpf(img_at(f, t.o000), img_at(f, t.o100), t.tx);
-  const float c10 = lerpf(img_at(f, t.o010), img_at(f, t.o110), t.tx);
-  const float c01 = lerpf(img_at(f, t.o001), img_at(f, t.o101), t.tx);
-  const float c11 = lerpf(img_at(f, t.o011), img_at(f, t.o111), t.tx);
-  return lerpf(lerpf(c00, c10, t.ty), lerpf(c01, c11, t.ty), t.tz);
-}
-
-// ---------------------------------------------------------------------------
-// pointwise data steps of Eq. (6) for a = w_hat - b_hat
-// ---------------------------------------------------------------------------
-// s = 2: v = a - J (J.a + r) / (theta + |J|^2)  (Sherman-Morrison)
-// s = 1: v = a - clip(z) J / theta,  z = theta (J.a + r) / (|J|^2 + eps)
-__device__ __forceinline__ void data_step(const float a[3], const float j[3], float r, float theta,
-                                          float eps, int data_term, float v[3]) {
-  const float ja = j[0] * a[0] + j[1] * a[1] + j[2] * a[2];
-  const float jj = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
-  float f;
-  if (data_term == 2) {
-    f = (ja + r) / (theta + jj);
-  } else {
-    const float z = theta * (ja + r) / (jj + eps);
-    f = (z / fmaxf(fabsf(z), 1.0f)) / theta;
-  }
-  v[0] = a[0] - j[0] * f;
-  v[1] = a[1] - j[1] * f;
-  v[2] = a[2] - j[2] * f;
-}
-
-// ---------------------------------------------------------------------------
-// Batches: pairs of one size are stored back to back in every buffer (a
-// scalar volume every V floats, a vector field every 3V, a half spectrum
-// every 3 (nx/2+1) ny nz complex); the pair of a workgroup is its last grid
-// index, and the kernels offset their pointers by it.
-// ---------------------------------------------------------------------------
-__host__ __device__ __forceinline__ size_t spectrum_elems(const Geo& g) {
-  return (size_t)3 * (g.nx / 2 + 1) * g.ny * g.nz;
-}
-template <typename P>
-__device__ __forceinline__ P* at_pair(P* p, size_t stride, int b) {
-  return p ? p + stride * (size_t)b : p;
 }
 
 // ---------------------------------------------------------------------------
@@ -712,7 +628,8 @@ constexpr int lane_budget_ce(int nlines) { return 1024 / nlines < 1 ? 1 : 1024 /
 template <int NY, int NZ>
 struct PlansCT {
   static constexpr TeamPlan PY = make_team_plan_ce(NY, lane_budget_ce(NZ));
-  static constexpr TeamPlan PZ = make_team_plan_ce(NZ, lane_budget_ce(NY));
+  static constexpr TeamPlan PZ0 = make_team_plan_ce(NZ, lane_budget_ce(NY), PLANE_Z_MIN_LANES);
+  static constexpr TeamPlan PZ = PZ0.nstages > 0 ? PZ0 : make_team_plan_ce(NZ, lane_budget_ce(NY));
   static constexpr TeamPlan PZI = reverse_team_plan_ce(PZ);
   static_assert(PY.nstages > 0 && PZ.nstages > 0, "no wave-team plan for this size");
   __device__ int ly() const { return PY.L; }
@@ -745,7 +662,7 @@ struct PlansCT {
 template <int NY, int NZ>
 __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan pz0, TeamPlan pzi0,
                                                  XDivs xd, int rs, Tables tg, float2* __restrict__ X,
-                                                 float lambda, float theta, int order) {
+                                                 float lambda, float theta, int order, int deriv) {
   extern __shared__ float2 lds[];
   // run-time plans are indexed by stage: keep them in LDS
   __shared__ __align__(16) unsigned char plan_mem[NY == 0 ? 3 * sizeof(TeamPlan) : 16];
@@ -868,7 +785,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
     for (int l0 = wave * nlw; l0 < ny; l0 += nwaves * nlw) {
       const int q = l0 + li;
       if (q < ny) {
-        const SpectralMult mult{sz, sx + sy[q], lambda, theta, inv_v, order};
+        const SpectralMult mult{sz, sx + sy[q], lambda, theta, inv_v, order, deriv};
         pol.z_fused(buf + lpad<4>(q), twz, tl, rs, mult);
       }
     }
@@ -949,7 +866,8 @@ __global__ void __launch_bounds__(256) k_split_rows(Geo g, FftPlan py, FastDiv d
 template <int NZ>
 __global__ void __launch_bounds__(256) k_split_cols(Geo g, FftPlan pz, FastDiv dl, FastDiv dz,
                                                      Tables t, float2* __restrict__ X,
-                                                     float lambda, float theta, int order) {
+                                                     float lambda, float theta, int order,
+                                                     int deriv) {
   extern __shared__ float2 lds[];
   const int ny = g.ny, nz = NZ ? NZ : g.nz, ls = lpad<4>(nz - 1) + 1, np = g.nx / 2 + 1;
   const int W = (int)dl.d, hw = W / 2;
@@ -981,7 +899,8 @@ __global__ void __launch_bounds__(256) k_split_cols(Geo g, FftPlan pz, FastDiv d
     const float k0 = kx + t.sy[q0 + l] + szl[r];
     float kn = k0;
     for (int i = 1; i < order; ++i) kn *= k0;
-    const float m = theta * inv * __builtin_amdgcn_rcpf(theta + lambda * kn);
+    const float rd = __builtin_amdgcn_rcpf(theta + lambda * kn);
+    const float m = deriv ? -theta * inv * kn * rd * rd : theta * inv * rd;
     float2& e = buf[l * ls + lpad<4>(r)];
     e = make_float2(e.x * m, e.y * m);
   }
@@ -1042,7 +961,8 @@ static bool split_shape_ok(const Geo& g) {
 }
 
 static hipError_t launch_pass_b_split(const Geo& g, const Tables& t, float2* X, float lambda,
-                                      float theta, int order, hipStream_t st, int batch) {
+                                      float theta, int order, hipStream_t st, int batch,
+                                      int deriv) {
   const SplitShape sh = split_shape(g);
   const FftPlan py = make_plan(g.ny), pz = make_plan(g.nz);
   const int np = g.nx / 2 + 1;
@@ -1061,7 +981,8 @@ static hipError_t launch_pass_b_split(const Geo& g, const Tables& t, float2* X, 
     default: NADMM_ROWS(0, INV); break;    \
   }
 #define NADMM_COLS(N) \
-  hipLaunchKernelGGL((k_split_cols<N>), cgrid, cblock, clds, st, g, pz, dw, dz, t, X, lambda, theta, order)
+  hipLaunchKernelGGL((k_split_cols<N>), cgrid, cblock, clds, st, g, pz, dw, dz, t, X, lambda, theta, order, \
+                     (int)deriv)
   NADMM_ROWS_NY(false);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1084,8 +1005,8 @@ static hipError_t launch_pass_b_split(const Geo& g, const Tables& t, float2* X, 
 static size_t pass_b_lds(const Geo& g) { return plane_lds_bytes(g, plane_row_stride(g)); }
 
 hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
-                         int order, hipStream_t st, int batch) {
-  if (!plane_fits(g)) return launch_pass_b_split(g, t, X, lambda, theta, order, st, batch);
+                         int order, hipStream_t st, int batch, bool deriv) {
+  if (!plane_fits(g)) return launch_pass_b_split(g, t, X, lambda, theta, order, st, batch, deriv);
   const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
   const dim3 grid(g.nx / 2 + 1, 3, batch), block(plane_team_threads(g));
   const size_t lds = pass_b_lds(g);
@@ -1095,7 +1016,7 @@ hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda,
 #define NADMM_PASS_B(NY_, NZ_)                                                                 \
   if (g.ny == NY_ && g.nz == NZ_) {                                                            \
     hipLaunchKernelGGL((k_pass_b<NY_, NZ_>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, \
-                       lambda, theta, order);                                                  \
+                       lambda, theta, order, (int)deriv);                                             \
     return hipGetLastError();                                                                  \
   }
   NADMM_PASS_B(32, 32) NADMM_PASS_B(32, 64) NADMM_PASS_B(32, 96) NADMM_PASS_B(32, 128)
@@ -1104,7 +1025,7 @@ hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda,
   NADMM_PASS_B(128, 32) NADMM_PASS_B(128, 64) NADMM_PASS_B(128, 96) NADMM_PASS_B(128, 128)
 #undef NADMM_PASS_B
   hipLaunchKernelGGL((k_pass_b<0, 0>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, lambda,
-                     theta, order);
+                     theta, order, (int)deriv);
   return hipGetLastError();
 }
 

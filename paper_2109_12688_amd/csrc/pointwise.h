@@ -1,0 +1,104 @@
+// Pointwise device helpers shared by the forward and the adjoint kernels:
+// periodic trilinear sampling, the data steps of Eq. (6) and batch offsets.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace nadmm {
+
+// ---------------------------------------------------------------------------
+// periodic trilinear sampling
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Grid voxel x plus displacement u, split exactly into the integer cell
+// (taken modulo n) and the fraction: floor(x + u) = x + floor(u) and
+// frac(x + u) = u - floor(u) since x is an integer.  Non-finite u gives a
+// valid cell and a NaN fraction, never an out-of-range index.
+__device__ __forceinline__ void cell(int x, float u, int n, int& i0, int& i1, float& t) {
+  const float fu = floorf(u);
+  t = u - fu;
+  const float cl = fminf(fmaxf(fu, -1.0e9f), 1.0e9f);
+  i0 = wrap_index(x + (int)cl, n);
+  i1 = (i0 + 1 == n) ? 0 : i0 + 1;
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+struct Tap {
+  int o000, o100, o010, o110, o001, o101, o011, o111;
+  float tx, ty, tz;
+};
+
+__device__ __forceinline__ Tap make_tap(int x, int y, int z, float ux, float uy, float uz,
+                                        const Geo& g) {
+  int x0, x1, y0, y1, z0, z1;
+  Tap t;
+  cell(x, ux, g.nx, x0, x1, t.tx);
+  cell(y, uy, g.ny, y0, y1, t.ty);
+  cell(z, uz, g.nz, z0, z1, t.tz);
+  const int r00 = (z0 * g.ny + y0) * g.nx, r01 = (z0 * g.ny + y1) * g.nx;
+  const int r10 = (z1 * g.ny + y0) * g.nx, r11 = (z1 * g.ny + y1) * g.nx;
+  t.o000 = r00 + x0; t.o100 = r00 + x1;
+  t.o010 = r01 + x0; t.o110 = r01 + x1;
+  t.o001 = r10 + x0; t.o101 = r10 + x1;
+  t.o011 = r11 + x0; t.o111 = r11 + x1;
+  return t;
+}
+
+// Image element as float32: bfloat16 is the upper half of a float32.
+__device__ __forceinline__ float img_at(const float* __restrict__ f, int i) { return f[i]; }
+__device__ __forceinline__ float img_at(const uint16_t* __restrict__ f, int i) {
+  return __uint_as_float((uint32_t)f[i] << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float sample(const T* __restrict__ f, const Tap& t) {
+  const float c00 = lerpf(img_at(f, t.o000), img_at(f, t.o100), t.tx);
+  const float c10 = lerpf(img_at(f, t.o010), img_at(f, t.o110), t.tx);
+  const float c01 = lerpf(img_at(f, t.o001), img_at(f, t.o101), t.tx);
+  const float c11 = lerpf(img_at(f, t.o011), img_at(f, t.o111), t.tx);
+  return lerpf(lerpf(c00, c10, t.ty), lerpf(c01, c11, t.ty), t.tz);
+}
+
+// ---------------------------------------------------------------------------
+// pointwise data steps of Eq. (6) for a = w_hat - b_hat
+// ---------------------------------------------------------------------------
+// s = 2: v = a - J (J.a + r) / (theta + |J|^2)  (Sherman-Morrison)
+// s = 1: v = a - clip(z) J / theta,  z = theta (J.a + r) / (|J|^2 + eps)
+__device__ __forceinline__ void data_step(const float a[3], const float j[3], float r, float theta,
+                                          float eps, int data_term, float v[3]) {
+  const float ja = j[0] * a[0] + j[1] * a[1] + j[2] * a[2];
+  const float jj = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+  float f;
+  if (data_term == 2) {
+    f = (ja + r) / (theta + jj);
+  } else {
+    const float z = theta * (ja + r) / (jj + eps);
+    f = (z / fmaxf(fabsf(z), 1.0f)) / theta;
+  }
+  v[0] = a[0] - j[0] * f;
+  v[1] = a[1] - j[1] * f;
+  v[2] = a[2] - j[2] * f;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: pairs of one size are stored back to back in every buffer (a
+// scalar volume every V floats, a vector field every 3V, a half spectrum
+// every 3 (nx/2+1) ny nz complex); the pair of a workgroup is its last grid
+// index, and the kernels offset their pointers by it.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ size_t spectrum_elems(const Geo& g) {
+  return (size_t)3 * (g.nx / 2 + 1) * g.ny * g.nz;
+}
+template <typename P>
+__device__ __forceinline__ P* at_pair(P* p, size_t stride, int b) {
+  return p ? p + stride * (size_t)b : p;
+}
+
+}  // namespace nadmm

@@ -258,6 +258,10 @@ WORKLOADS = {
     # 128x128x96 heart phantom, n=2, lambda=0.01, theta=0.1, 10 x 20
     "phantom128x128x96": dict(dims=(128, 128, 96), seed=1, kind="phantom", max_disp=8.0,
                               lam=0.01, theta=0.1, order=2, outer=10, iters=20),
+    # 96^3 blob pair for the differentiated warping: one warping of 20
+    # iterations, gradients checkpointed every 5 iterations
+    "blobs96": dict(dims=(96, 96, 96), seed=3, kind="blobs", max_disp=5.0,
+                    lam=0.01, theta=0.1, order=2, outer=1, iters=20, checkpoint=5),
     # 192x192x128 heart phantom (geometry scaled with the volume), images
     # stored as bfloat16 by the precision study; n=3, lambda=0.005, 10 x 30
     "phantom192x192x128": dict(dims=(192, 192, 128), seed=4, kind="phantom", max_disp=8.0,

@@ -15,7 +15,12 @@ For each run: the displacement and warped intensity at a fixed seeded sample
 of voxels, the Jacobian statistics of the whole displacement, SSD before and
 after, and a checksum of the inputs.
 
-    python tests/golden/make_golden.py [phantom128x128x96 | phantom192x192x128]
+* blobs96: the 96^3 blob pair's one-warping image match (20 iterations,
+  n = 2, lambda = 0.01, theta = 0.1): loss, dL/dlambda and dL/dI1 at the
+  sampled voxels and at 16 further seeded voxels (the finite-difference
+  probes of the GPU test).
+
+    python tests/golden/make_golden.py [phantom128x128x96 | phantom192x192x128 | blobs96]
 """
 import hashlib
 import json
@@ -65,7 +70,35 @@ def main(name):
     idx = sample_indices(pair.fixed.shape, NSAMPLE)
     out = {"workload": name, "params": {k: w[k] for k in ("lam", "theta", "order", "outer", "iters")},
            "sample_seed": 7, "indices": idx.tolist()}
-    if name == "phantom192x192x128":
+    if name == "blobs96":
+        rng = np.random.default_rng(31)
+        fd_idx = np.sort(rng.choice(int(np.prod(pair.fixed.shape)), size=16, replace=False))
+        loss, gm, gl = O.ssd_one_warping_grad(pair.fixed, pair.moving, w["lam"], w["theta"],
+                                              w["order"], w["iters"])
+        out["source"] = ("oracle.ssd_one_warping_grad (FP64 NumPy, reverse mode through the "
+                         "iterations): loss, dL/dlambda and dL/dmoving at sampled voxels")
+        out["input_sha256"] = input_digest(pair.fixed.astype(np.float32), pair.moving.astype(np.float32))
+        out["loss"] = loss
+        out["d_lambda"] = gl
+        out["d_moving"] = [float(f"{v:.12g}") for v in gm.reshape(-1)[idx]]
+        out["fd_indices"] = fd_idx.tolist()
+        out["d_moving_fd_indices"] = [float(f"{v:.12g}") for v in gm.reshape(-1)[fd_idx]]
+        # central differences of the FP64 loss, eps = 1e-3, at the same voxels and lambda
+        eps = 1e-3
+        args = (w["theta"], w["order"], w["iters"])
+        mf = pair.moving.astype(np.float64).reshape(-1)
+        fd = []
+        for i in fd_idx:
+            mp, mm = mf.copy(), mf.copy()
+            mp[i] += eps
+            mm[i] -= eps
+            lp = O.ssd_one_warping(pair.fixed, mp.reshape(pair.moving.shape), w["lam"], *args)
+            lm = O.ssd_one_warping(pair.fixed, mm.reshape(pair.moving.shape), w["lam"], *args)
+            fd.append((lp - lm) / (2 * eps))
+        out["fd_moving_eps1e-3"] = fd
+        out["fd_lambda_eps1e-3"] = (O.ssd_one_warping(pair.fixed, pair.moving, w["lam"] + eps, *args)
+                                    - O.ssd_one_warping(pair.fixed, pair.moving, w["lam"] - eps, *args)) / (2 * eps)
+    elif name == "phantom192x192x128":
         fb, mb = synth.bf16_bits(pair.fixed), synth.bf16_bits(pair.moving)
         out["source"] = ("oracle.register (FP64 NumPy), whole registration; 'bf16': on the "
                          "bfloat16-rounded images, 'fp32': on the float32 images")

@@ -441,3 +441,80 @@ def test_p15_divergence_is_visible_in_residuals():
     res2 = O.admm(0.3 * J, r, 0.5, 0.1, 1, 200, history=True)
     p2 = np.array([h["primal"] for h in res2.history])
     assert p2[-1] < 1e-8 * p2[0]
+
+
+# ---------------------------------------------------------------------------
+# P16-P19: the adjoint of one warping (reverse mode through Eq. (5), (6))
+# ---------------------------------------------------------------------------
+def _smooth(d, seed):
+    return synth.random_volume(d, seed=seed, smooth_kmax=2).astype(np.float64)
+
+
+def test_p16_warp_transpose_is_adjoint():
+    d = (7, 6, 5)
+    rng = np.random.default_rng(160)
+    f = rng.standard_normal(d[::-1])
+    g = rng.standard_normal(d[::-1])
+    u = 2.5 * rng.standard_normal((3,) + d[::-1])
+    lhs = np.sum(O.trilinear_periodic(f, u) * g)
+    rhs = np.sum(f * O.trilinear_transpose(g, u))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_p17_position_gradient_matches_differences():
+    d = (8, 7, 6)
+    rng = np.random.default_rng(170)
+    f = rng.standard_normal(d[::-1])
+    u = 1.7 * rng.standard_normal((3,) + d[::-1])
+    # stay away from cell faces, where the one-sided derivative jumps
+    frac = u - np.floor(u)
+    u = np.floor(u) + np.clip(frac, 0.05, 0.95)
+    grad = O.trilinear_position_gradient(f, u)
+    h = 1e-6
+    for c in range(3):
+        e = np.zeros_like(u)
+        e[c] = h
+        fd = (O.trilinear_periodic(f, u + e) - O.trilinear_periodic(f, u - e)) / (2 * h)
+        assert np.abs(fd - grad[c]).max() < 1e-7
+
+
+def test_p18_data_step_adjoint_matches_differences():
+    rng = np.random.default_rng(180)
+    shp = (3, 4, 3, 5)
+    a, J, gv = (rng.standard_normal(shp) for _ in range(3))
+    r = rng.standard_normal(shp[1:])
+    theta = 0.3
+    ga, gJ, gr = O.v_step_l2_adjoint(gv, a, J, r, theta)
+    h = 1e-6
+    for x, gx in ((a, ga), (J, gJ)):
+        dx = rng.standard_normal(shp)
+        pa = O.v_step_l2(a + h * dx if x is a else a, J + h * dx if x is J else J, r, theta)
+        ma = O.v_step_l2(a - h * dx if x is a else a, J - h * dx if x is J else J, r, theta)
+        fd = np.sum(gv * (pa - ma)) / (2 * h)
+        assert abs(fd - np.sum(gx * dx)) < 1e-7 * max(1.0, abs(fd))
+    dr = rng.standard_normal(shp[1:])
+    fd = np.sum(gv * (O.v_step_l2(a, J, r + h * dr, theta) - O.v_step_l2(a, J, r - h * dr, theta))) / (2 * h)
+    assert abs(fd - np.sum(gr * dr)) < 1e-7 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("order,iters", [(1, 3), (2, 6)])
+def test_p19_one_warping_gradient_matches_differences(order, iters):
+    d = (10, 8, 6)
+    f = _smooth(d, 190)
+    m = _smooth(d, 191)
+    lam, theta = 0.05, 0.1
+    loss, gm, gl = O.ssd_one_warping_grad(f, m, lam, theta, order, iters)
+    assert abs(loss - O.ssd_one_warping(f, m, lam, theta, order, iters)) < 1e-12 * loss
+    rng = np.random.default_rng(192)
+    h = 1e-6
+    for _ in range(6):
+        i = tuple(int(rng.integers(0, n)) for n in m.shape)
+        mp, mm = m.copy(), m.copy()
+        mp[i] += h
+        mm[i] -= h
+        fd = (O.ssd_one_warping(f, mp, lam, theta, order, iters)
+              - O.ssd_one_warping(f, mm, lam, theta, order, iters)) / (2 * h)
+        assert abs(fd - gm[i]) < 1e-6 * max(1.0, abs(fd)), (i, fd, gm[i])
+    fd = (O.ssd_one_warping(f, m, lam + h, theta, order, iters)
+          - O.ssd_one_warping(f, m, lam - h, theta, order, iters)) / (2 * h)
+    assert abs(fd - gl) < 1e-6 * max(1.0, abs(fd)), (fd, gl)
