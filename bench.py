@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch of 32 uneven pairs (batched vs one-by-one)")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the gradient of one warping at 96^3")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the bfloat16-image run at 192x192x128 (vs the float32 path)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -168,6 +170,8 @@ def generate_inputs(args):
     jobs = {"main": (synth.make_pair, args.workload)}
     if not args.no_bf16:
         jobs["bf16"] = (synth.make_pair, "phantom192x192x128")
+    if not args.no_grad:
+        jobs["grad"] = (synth.make_pair, "blobs96")
     if not args.no_batch:
         for i, spec in enumerate(synth.batch_specs(32)):
             jobs[("batch", i)] = (synth.batch_pair, spec)
@@ -242,6 +246,37 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
             "pairs_per_s_batched": round(1000.0 * len(specs) / t_batch, 2),
             "batched_vs_one_by_one": round(t_plain / t_batch, 4),
             "bit_identical": bool(same)}
+
+
+def grad_time(api, torch, synth, pair, reps=5):
+    """The differentiated warping at 96^3 (20 iterations, checkpoints every
+    5): ms per call of the gradient entry point (loss, dL/dmoving,
+    dL/dlambda), against one forward warping (nadmm_register, 1 x 20)."""
+    name = "blobs96"
+    w = synth.WORKLOADS[name]
+    f, m = torch.from_numpy(pair.fixed).cuda(), torch.from_numpy(pair.moving).cuda()
+    args = (w["lam"], w["theta"], w["order"], w["iters"])
+    ws = api.workspace_grad(pair.fixed.shape, *args, w["checkpoint"])
+    wsr = api.workspace(pair.fixed.shape)
+    stream = torch.cuda.current_stream()
+
+    def ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_grad = ms(lambda: api.ssd_grad(f, m, *args, checkpoint=w["checkpoint"], ws=ws))
+    t_fwd = ms(lambda: api.register(f, m, w["lam"], w["theta"], w["order"], 1, w["iters"], ws=wsr))
+    log(f"{name}: gradient {t_grad:.3f} ms, forward warping {t_fwd:.3f} ms")
+    return {"workload": name, "dims_xyz": list(w["dims"]), "iters": w["iters"],
+            "checkpoint": w["checkpoint"], "steps": reps, "ms_per_gradient": round(t_grad, 3),
+            "ms_per_forward_warping": round(t_fwd, 3), "gradient_vs_forward": round(t_grad / t_fwd, 3)}
 
 
 def bf16_vs_plain(api, torch, synth, pair, reps=3):
@@ -413,6 +448,8 @@ def main():
     }
     if not args.no_bf16:
         res["bf16"] = bf16_vs_plain(api, torch, synth, inputs["bf16"])
+    if not args.no_grad:
+        res["grad"] = grad_time(api, torch, synth, inputs["grad"])
     if not args.no_batch:
         res["batch"] = batch_vs_plain(api, torch, synth,
                                       [inputs[("batch", i)] for i in range(32)])

@@ -659,10 +659,11 @@ struct PlansCT {
 };
 
 // NY = NZ = 0: any size (run-time plans); otherwise the sizes are fixed.
-template <int NY, int NZ>
+// DERIV: multiply by d/dlambda of the multiplier (generic kernel only).
+template <int NY, int NZ, bool DERIV = false>
 __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan pz0, TeamPlan pzi0,
                                                  XDivs xd, int rs, Tables tg, float2* __restrict__ X,
-                                                 float lambda, float theta, int order, int deriv) {
+                                                 float lambda, float theta, int order) {
   extern __shared__ float2 lds[];
   // run-time plans are indexed by stage: keep them in LDS
   __shared__ __align__(16) unsigned char plan_mem[NY == 0 ? 3 * sizeof(TeamPlan) : 16];
@@ -785,7 +786,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
     for (int l0 = wave * nlw; l0 < ny; l0 += nwaves * nlw) {
       const int q = l0 + li;
       if (q < ny) {
-        const SpectralMult mult{sz, sx + sy[q], lambda, theta, inv_v, order, deriv};
+        const SpectralMult mult{sz, sx + sy[q], lambda, theta, inv_v, order, DERIV ? 1 : 0};
         pol.z_fused(buf + lpad<4>(q), twz, tl, rs, mult);
       }
     }
@@ -1016,21 +1017,27 @@ hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda,
 #define NADMM_PASS_B(NY_, NZ_)                                                                 \
   if (g.ny == NY_ && g.nz == NZ_) {                                                            \
     hipLaunchKernelGGL((k_pass_b<NY_, NZ_>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, \
-                       lambda, theta, order, (int)deriv);                                             \
+                       lambda, theta, order);                                                         \
     return hipGetLastError();                                                                  \
   }
+  if (!deriv) {  // the specialised kernels carry the multiplier only
   NADMM_PASS_B(32, 32) NADMM_PASS_B(32, 64) NADMM_PASS_B(32, 96) NADMM_PASS_B(32, 128)
   NADMM_PASS_B(64, 32) NADMM_PASS_B(64, 64) NADMM_PASS_B(64, 96) NADMM_PASS_B(64, 128)
   NADMM_PASS_B(96, 32) NADMM_PASS_B(96, 64) NADMM_PASS_B(96, 96) NADMM_PASS_B(96, 128)
   NADMM_PASS_B(128, 32) NADMM_PASS_B(128, 64) NADMM_PASS_B(128, 96) NADMM_PASS_B(128, 128)
+  }
 #undef NADMM_PASS_B
-  hipLaunchKernelGGL((k_pass_b<0, 0>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, lambda,
-                     theta, order, (int)deriv);
+  if (deriv)
+    hipLaunchKernelGGL((k_pass_b<0, 0, true>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X,
+                       lambda, theta, order);
+  else
+    hipLaunchKernelGGL((k_pass_b<0, 0>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, lambda,
+                       theta, order);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// pass C: packed half spectrum -> y = S t, then the mode's pointwise work
+// pass C: half spectrum -> y = S t, then the mode's pointwise work
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
