@@ -89,7 +89,7 @@ const char* nadmm_last_error(void);
 
 /* Size in bytes (written to host *bytes) of the workspace that every entry
  * point below accepts for these dimensions.  `p` may be NULL (the size does
- * not depend on the parameters).  About 17 float32 values per voxel. */
+ * not depend on the parameters).  About 14 float32 values per voxel. */
 nadmm_status nadmm_workspace_size(nadmm_dims d, const nadmm_params* p, size_t* bytes);
 
 /* Full registration: the iterative scheme of Sec. 2 with the

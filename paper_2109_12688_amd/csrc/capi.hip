@@ -129,10 +129,10 @@ nadmm_status check_ptr(const void* p, const char* name, bool nullable) {
     if (s_ != NADMM_OK) return s_;          \
   } while (0)
 
-// Workspace: 17 float32 fields of V values (each region 256-byte aligned),
+// Workspace: 14 float32 fields of V values (each region 256-byte aligned),
 // the Jacobian partials and the transform tables (a few KB).
 struct Layout {
-  size_t J, r, iw, s1, s2, X, u, jac, tab, total;
+  size_t r, iw, s1, s2, X, u, jac, tab, total;
 };
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -144,7 +144,6 @@ Layout layout(const nadmm_dims& d, int batch = 1) {
   const size_t f3 = align256(B * 3 * V * sizeof(float)), f1 = align256(B * V * sizeof(float));
   Layout L;
   size_t o = 0;
-  L.J = o; o += f3;
   L.r = o; o += f1;
   L.iw = o; o += f1;
   L.s1 = o; o += f3;
@@ -228,10 +227,11 @@ hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const
 // pass A of the next solve's input, then pass B).  On return *cur holds
 // s^{iters-1} and X the pass-B output for S s^{iters-1}, ready for the
 // warping's final pass C.
+// J given, or (J null) recomputed in the fused pass from the warped source iw.
 nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
-                             const nadmm_params* p, const float* J, const float* r, float*& cur,
-                             float*& prev, float2* X, float* v_last, hipStream_t st,
-                             int batch = 1) {
+                             const nadmm_params* p, const float* J, const float* iw,
+                             const float* r, float*& cur, float*& prev, float2* X, float* v_last,
+                             hipStream_t st, int batch = 1) {
   const std::vector<double> gam = nesterov_gammas(p->iters);
   HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st, batch));  // gamma_0 = 0: t = s^0
   for (int k = 1; k < p->iters; ++k) {
@@ -242,6 +242,7 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     a.gamma = (float)gam[k - 1];
     a.gamma_next = (k + 1 < p->iters) ? (float)gam[k] : 0.0f;  // the final solve takes s as is
     a.J = J;
+    a.iw = iw;
     a.r = r;
     a.theta = (float)p->theta;
     a.eps = (float)p->eps;
@@ -249,7 +250,7 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     a.out = prev;  // s^k overwrites s^{k-2} voxel by voxel
     a.v_out = (k == p->iters - 1) ? v_last : nullptr;
     HIP_TRY(timed(KK_PASS_CA_ITER, st, [&] {
-      return launch_pass_c(g, pl.x, tb, kIterFwd, a, st, batch);
+      return launch_pass_c(g, pl.x, tb, J ? kIterFwd : kIterFwdIw, a, st, batch);
     }));
     HIP_TRY(timed(KK_PASS_B, st, [&] {
       return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch);
@@ -283,7 +284,6 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
   const Layout L = layout(d, batch);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t V = (size_t)g.V;
-  float* J = at<float>(workspace, L.J);
   float* r = at<float>(workspace, L.r);
   float* iw = at<float>(workspace, L.iw);
   float* S1 = at<float>(workspace, L.s1);
@@ -314,11 +314,12 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
   for (int c = 0; c < p->outer; ++c) {
     const bool last = (c == p->outer - 1);
     // linearised data term at the current warp, and s^0 (Eq. (6) from zero)
-    HIP_TRY(timed(KK_GRAD, st, [&] { return launch_grad_resid(g, iw, fixed, J, r, S1, (float)p->theta, (float)p->eps,
+    // r and s^0 only: the iterations recompute J = grad I1^w from iw
+    HIP_TRY(timed(KK_GRAD, st, [&] { return launch_grad_resid(g, iw, fixed, nullptr, r, S1, (float)p->theta, (float)p->eps,
                               p->data_term, st, batch); }));
     float* cur = S1;
     float* prev = S2;
-    CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, nullptr, st, batch));
+    CHECK(admm_iterations(g, pl, tb, p, nullptr, iw, r, cur, prev, X, nullptr, st, batch));
     // final w = S s^{K-1}, composed onto the displacement
     PassCArgs a{};
     a.X = X;
@@ -592,7 +593,7 @@ nadmm_status nadmm_admm(nadmm_dims d, const nadmm_params* p, const float* J, con
                            (float)p->eps, p->data_term, st); }));
   float* cur = S1;
   float* prev = S2;
-  CHECK(admm_iterations(g, pl, tb, p, J, r, cur, prev, X, v_out, st));
+  CHECK(admm_iterations(g, pl, tb, p, J, nullptr, r, cur, prev, X, v_out, st));
   PassCArgs a{};
   a.X = X;
   a.s1 = cur;
@@ -709,7 +710,6 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   const Plans pl = plans(d);
   const Layout L = layout(d);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  float* J = at<float>(workspace, L.J);
   float* r = at<float>(workspace, L.r);
   float* S1 = at<float>(workspace, L.s1);
   float* S2 = at<float>(workspace, L.s2);
@@ -724,7 +724,7 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   a.s2 = S2;
   a.gamma = 0.0f;
   a.gamma_next = 0.0f;
-  a.J = J;
+  a.iw = at<float>(workspace, L.iw);
   a.r = r;
   a.theta = (float)p->theta;
   a.eps = (float)p->eps;
@@ -733,7 +733,7 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   auto launch = [&]() -> hipError_t {
     if (kind == 0) return launch_pass_a(g, pl.x, tb, S1, nullptr, 0.0f, X, st);
     if (kind == 1) return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
-    return launch_pass_c(g, pl.x, tb, kIterFwd, a, st);
+    return launch_pass_c(g, pl.x, tb, kIterFwdIw, a, st);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));

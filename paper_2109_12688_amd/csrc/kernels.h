@@ -72,7 +72,11 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 // the next solve (t' = s^k + gamma_next (s^k - s^{k-1}) transformed along x
 // and written back over the spectrum the pass read).
 // kComposeBf16 is kCompose with the moving image stored as bfloat16.
-enum PassCMode { kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4 };
+// kIterFwdIw is kIterFwd with J recomputed from the warped source iw (the
+// periodic central differences of k_grad_resid) instead of read.
+enum PassCMode {
+  kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4, kIterFwdIw = 5
+};
 
 struct PassCArgs {
   float2* X;         // read; kIterFwd also writes the next half spectrum here
@@ -80,7 +84,8 @@ struct PassCArgs {
   const float* s2;   // s^{k-2} or nullptr when gamma = 0
   float gamma;
   float gamma_next;  // kIterFwd: extrapolation weight of the next solve's input
-  const float* J;
+  const float* J;    // kIterFwd
+  const float* iw;   // kIterFwdIw: warped source; J = its central differences
   const float* r;
   float theta;
   float eps;

@@ -1048,6 +1048,26 @@ __device__ __forceinline__ void f4set(float4& v, int e, float s) {
   if (e == 0) v.x = s; else if (e == 1) v.y = s; else if (e == 2) v.z = s; else v.w = s;
 }
 
+// J = grad I1^w at the 4 voxels (x0 .. x0+3, y, z) of a run: periodic central
+// differences with unit spacing, the same operations as k_grad_resid.
+__device__ __forceinline__ void run_gradient(const Geo& g, int nx, const float* __restrict__ iw,
+                                             int x0, int y, int z, float4 J[3]) {
+  const int ny = g.ny, nz = g.nz;
+  const float* row = iw + (size_t)(z * ny + y) * nx;
+  const float4 c = ld4(row + x0);
+  const float xm = row[x0 == 0 ? nx - 1 : x0 - 1];
+  const float xp = row[x0 + 4 == nx ? 0 : x0 + 4];
+  const float4 ym = ld4(iw + (size_t)(z * ny + (y == 0 ? ny - 1 : y - 1)) * nx + x0);
+  const float4 yp = ld4(iw + (size_t)(z * ny + (y + 1 == ny ? 0 : y + 1)) * nx + x0);
+  const float4 zm = ld4(iw + (size_t)((z == 0 ? nz - 1 : z - 1) * ny + y) * nx + x0);
+  const float4 zp = ld4(iw + (size_t)((z + 1 == nz ? 0 : z + 1) * ny + y) * nx + x0);
+  J[0] = make_float4((c.y - xm) * 0.5f, (c.z - c.x) * 0.5f, (c.w - c.y) * 0.5f, (xp - c.z) * 0.5f);
+  J[1] = make_float4((yp.x - ym.x) * 0.5f, (yp.y - ym.y) * 0.5f, (yp.z - ym.z) * 0.5f,
+                     (yp.w - ym.w) * 0.5f);
+  J[2] = make_float4((zp.x - zm.x) * 0.5f, (zp.y - zm.y) * 0.5f, (zp.z - zm.z) * 0.5f,
+                     (zp.w - zm.w) * 0.5f);
+}
+
 template <int MODE, int NX>
 __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx, PassCArgs a) {
@@ -1061,6 +1081,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
     a.s2 = at_pair(a.s2, v3, b);
     a.J = at_pair(a.J, v3, b);
     a.r = at_pair(a.r, v1, b);
+    a.iw = at_pair(a.iw, v1, b);
     a.out = at_pair(a.out, v3, b);
     a.v_out = at_pair(a.v_out, v3, b);
     a.b_out = at_pair(a.b_out, v3, b);
@@ -1138,7 +1159,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
     return bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<XL_PADSH>(4 * x4)) + (yy & 1);
   };
   float4 yv[MI][3];
-  if (MODE != kIterFwd) {
+  if (MODE != kIterFwd && MODE != kIterFwdIw) {
 #pragma unroll
     for (int it = 0; it < MI; ++it)
       if (threadIdx.x + it * nthr < nitems)
@@ -1155,7 +1176,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
       if (threadIdx.x + it * nthr < nitems)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
-  } else if (MODE == kIterFwd) {
+  } else if (MODE == kIterFwd || MODE == kIterFwdIw) {
     // one run at a time keeps the register footprint small (occupancy hides
     // the latency); out may alias s2, and each run is read and written by
     // the same thread only
@@ -1164,14 +1185,16 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
       const int idx = threadIdx.x + it * nthr;
       if (idx >= nitems) break;
       const int yy = (int)fdiv((uint32_t)idx, xd.q4);
-      const int go = (z * g.ny + y0 + yy) * nx + 4 * (idx - yy * q4);
+      const int x0 = 4 * (idx - yy * q4);
+      const int go = (z * g.ny + y0 + yy) * nx + x0;
       float4 s1v[3], s2v[3], jv[3], yr[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         s1v[c] = ld4(a.s1 + c * g.V + go);
         s2v[c] = a.s2 ? ld4(a.s2 + c * g.V + go) : s1v[c];
-        jv[c] = ld4(a.J + c * g.V + go);
+        if constexpr (MODE == kIterFwd) jv[c] = ld4(a.J + c * g.V + go);
       }
+      if constexpr (MODE == kIterFwdIw) run_gradient(g, nx, a.iw, x0, y0 + yy, z, jv);
       const float4 rv = ld4(a.r + go);
       float* slot[3];
 #pragma unroll
@@ -1286,6 +1309,7 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
   switch (mode) {
     case kOutY: NADMM_PASS_C_NX(kOutY); break;
     case kIterFwd: NADMM_PASS_C_NX(kIterFwd); break;
+    case kIterFwdIw: NADMM_PASS_C_NX(kIterFwdIw); break;
     case kFinalWB: NADMM_PASS_C_NX(kFinalWB); break;
     case kComposeBf16: NADMM_PASS_C_NX(kComposeBf16); break;
     default: NADMM_PASS_C_NX(kCompose); break;

@@ -60,9 +60,9 @@ def test_workspace_size(lib):
     st, n = ws_size(lib, Dims(128, 128, 96))
     assert st == 0
     V = 128 * 128 * 96
-    # 17 float32 fields of V voxels, the extra Nyquist plane of the packed
-    # half spectrum (3 components x ny*nz complex), plus transform tables
-    base = 17 * 4 * V + 3 * 128 * 96 * 8
+    # 14 float32 fields of V voxels, the extra Nyquist plane of the half
+    # spectrum (3 components x ny*nz complex), plus transform tables
+    base = 14 * 4 * V + 3 * 128 * 96 * 8
     assert base <= n <= base + 64 * 1024
     assert lib.nadmm_workspace_size(Dims(128, 128, 96), None, None) == 1
 
@@ -71,7 +71,7 @@ def test_workspace_size(lib):
 def test_large_planes_supported(lib, d):
     st, n = ws_size(lib, Dims(*d))
     assert st == 0, lib.nadmm_last_error()
-    assert n >= 17 * 4 * d[0] * d[1] * d[2]
+    assert n >= 14 * 4 * d[0] * d[1] * d[2]
 
 
 @pytest.mark.parametrize("d", [(128, 128, 7), (6, 4, 4), (128, 129, 96), (512, 16, 16),
