@@ -221,6 +221,9 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
     wsb = {d: api.workspace_batch((d[2], d[1], d[0]), len(idx)) for d, idx in groups.items()}
     streams = {d: torch.cuda.Stream() for d in groups}
     bouts = {}
+    tiles = {"x".join(map(str, d)): api.autotune((d[2], d[1], d[0]), w["lam"], w["theta"], w["order"],
+                                                  batch=len(idx), ws=wsb[d])
+             for d, idx in groups.items()}
 
     def batched():
         cur = torch.cuda.current_stream()
@@ -246,16 +249,41 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
 
     t_plain = ms(plain)
     t_batch = ms(batched)
+    # the batched set captured once in a graph per size class (launch work
+    # recorded, replayed on the same streams)
+    graphs = {}
+    for d in groups:
+        s = streams[d]
+        s.wait_stream(torch.cuda.current_stream())
+        graphs[d] = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graphs[d], stream=s):
+            api.register_batch(stacked[d][0], stacked[d][1], *args, ws=wsb[d], out=bouts[d])
+    torch.cuda.synchronize()
+
+    def batched_graph():
+        cur = torch.cuda.current_stream()
+        for d in groups:
+            s = streams[d]
+            s.wait_stream(cur)
+            with torch.cuda.stream(s):
+                graphs[d].replay()
+        for d in groups:
+            cur.wait_stream(streams[d])
+
+    t_graph = ms(batched_graph)
     same = all(torch.equal(bouts[d]["disp"][j], outs[i]["disp"]) for d, idx in groups.items()
-               for j, i in enumerate(idx))
+               for j, i in enumerate(idx))  # after the graph replays
     nvox = int(sum(np.prod(d) for d, _ in specs))
     log(f"batch of {len(specs)}: one by one {t_plain:.2f} ms, batched {t_batch:.2f} ms")
     return {"pairs": len(specs), "sizes": {"x".join(map(str, d)): len(idx) for d, idx in groups.items()},
             "voxels": nvox, "outer": w["outer"], "iters": w["iters"], "steps": reps,
             "ms_one_by_one": round(t_plain, 3), "ms_batched": round(t_batch, 3),
+            "ms_batched_graph": round(t_graph, 3),
             "pairs_per_s_one_by_one": round(1000.0 * len(specs) / t_plain, 2),
             "pairs_per_s_batched": round(1000.0 * len(specs) / t_batch, 2),
             "batched_vs_one_by_one": round(t_plain / t_batch, 4),
+            "batched_graph_vs_one_by_one": round(t_plain / t_graph, 4),
+            "tile_rows": tiles,
             "bit_identical": bool(same)}
 
 
@@ -383,6 +411,8 @@ def main():
     copy_gbs = 2 * copy_probe_bytes(V) / (c0.elapsed_time(c1) / ncopy * 1e-3) / 1e9
     del src, dst
 
+    tile_rows = api.autotune(shp, w["lam"], w["theta"], w["order"], ws=ws)
+    log(f"x-line tile: {tile_rows} rows per workgroup")
     log("warmup")
     for _ in range(args.warmup):
         step()
@@ -468,7 +498,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "dims_xyz": list(w["dims"]), "outer": w["outer"],
                    "iters": w["iters"], "order": w["order"], "lambda": w["lam"], "theta": w["theta"],
-                   "parallelism": "single-gpu"},
+                   "parallelism": "single-gpu", "tile_rows": tile_rows},
         "roofline": roofline,
         "rooflines": rooflines,
         "kernels": kernels,

@@ -141,6 +141,19 @@ nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_param
                                   const float* init_disp, float* disp, float* warped,
                                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* Tile autotuner: times the fused x-line pass of the iteration for every
+ * admissible number of y rows per workgroup (even divisors of ny up to 32
+ * that fit the kernels' per-thread bounds), `reps` = 20 launches each
+ * between HIP events on `stream` (the call waits for them), and keeps the
+ * fastest for all later calls with these dims in this process (a
+ * process-wide table; tuning while other threads run the same dims changes
+ * only their speed).  Results of every entry point are bit for bit the same
+ * for any choice.  `workspace` (nadmm_workspace_size_batch(d, batch) bytes)
+ * is scratch; the chosen rows go to host *rows (may be NULL).  Not for use
+ * inside stream capture. */
+nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, void* workspace,
+                            size_t workspace_bytes, void* stream, int32_t* rows);
+
 /* Gradient of one warping's image match (the differentiated hot path):
  *   L = sum_x (I1(x + w(x)) - I0(x))^2,
  * with w the velocity of ONE warping from u = 0 (Sec. 2): `p->iters`

@@ -51,6 +51,8 @@ _SIGS = {
                                   ctypes.c_int),
     "nadmm_ssd_grad": ([Dims, ctypes.POINTER(Params), ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                        ctypes.c_int),
+    "nadmm_autotune": ([Dims, ctypes.c_int32, ctypes.POINTER(Params), _P, ctypes.c_size_t, _P,
+                        ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "nadmm_admm": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_fourier_solve": ([Dims, ctypes.POINTER(Params), _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_warp": ([Dims, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),

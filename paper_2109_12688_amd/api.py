@@ -174,6 +174,19 @@ def ssd_grad(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float
     return loss, dmov, dlam
 
 
+def autotune(vol_shape, lam: float, theta: float, order: int, batch: int = 1,
+             ws: torch.Tensor | None = None, device="cuda") -> int:
+    """Pick and keep the fastest x-line tile for these sizes (see
+    nadmm_autotune); returns the rows per workgroup chosen."""
+    if ws is None:
+        ws = workspace_batch(vol_shape, batch, device)
+    rows = ctypes.c_int32(0)
+    p = params(lam, theta, order)
+    _lib.call("nadmm_autotune", dims_of(vol_shape), ctypes.c_int32(batch), ctypes.byref(p), _ptr(ws),
+              ctypes.c_size_t(ws.numel()), _stream(), ctypes.byref(rows))
+    return int(rows.value)
+
+
 def admm(J: torch.Tensor, r: torch.Tensor, lam: float, theta: float, order: int, iters: int,
          data_term: int = 2, eps: float = 1e-8, ws: torch.Tensor | None = None):
     """``iters`` ADMM iterations from zero for a given J, r.  Returns (w, b, v)."""

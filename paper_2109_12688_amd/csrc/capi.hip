@@ -445,6 +445,68 @@ nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_param
                        workspace_bytes, stream, batch);
 }
 
+nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, void* workspace,
+                            size_t workspace_bytes, void* stream, int32_t* rows_out) {
+  CHECK(check_dims(d));
+  CHECK(check_batch(batch));
+  CHECK(check_params(p, false));
+  CHECK(check_ws(d, workspace, workspace_bytes, batch));
+  const Geo g = geo(d);
+  const Plans pl = plans(d);
+  const Layout L = layout(d, batch);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t V = (size_t)g.V, B = (size_t)batch;
+  const Tables tb = tables_at(g, at<char>(workspace, L.tab));
+  HIP_TRY(launch_tables(g, tb, st));
+  // defined contents for the timed launches (the values do not matter)
+  HIP_TRY(launch_fill(at<float>(workspace, L.r), 0.0f, B * V, st));
+  HIP_TRY(launch_fill(at<float>(workspace, L.iw), 0.0f, B * V, st));
+  HIP_TRY(launch_fill(at<float>(workspace, L.s1), 0.0f, 3 * B * V, st));
+  HIP_TRY(launch_fill(at<float>(workspace, L.s2), 0.0f, 3 * B * V, st));
+  HIP_TRY(launch_fill(at<float>(workspace, L.X), 0.0f,
+                      B * 3 * (size_t)(d.nx / 2 + 1) * d.ny * d.nz * 2, st));
+  PassCArgs a{};
+  a.X = at<float2>(workspace, L.X);
+  a.s1 = at<float>(workspace, L.s1);
+  a.s2 = at<float>(workspace, L.s2);
+  a.iw = at<float>(workspace, L.iw);
+  a.r = at<float>(workspace, L.r);
+  a.theta = (float)p->theta;
+  a.eps = (float)p->eps;
+  a.data_term = p->data_term;
+  a.out = at<float>(workspace, L.s2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t err = hipEventCreate(&e1);
+  int best = 0;
+  float best_ms = 0.f;
+  const int reps = 20;
+  for (int rows = 2; rows <= 32 && err == hipSuccess; rows += 2) {
+    if (g.ny % rows) continue;
+    xline_rows_set(g, rows);
+    if (!launch_shape_ok(g)) continue;
+    for (int i = 0; i < 2 && err == hipSuccess; ++i)
+      err = launch_pass_c(g, pl.x, tb, kIterFwdIw, a, st, batch);
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && err == hipSuccess; ++i)
+      err = launch_pass_c(g, pl.x, tb, kIterFwdIw, a, st, batch);
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && (best == 0 || ms < best_ms)) {
+      best = rows;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  xline_rows_set(g, best);  // 0 (nothing timed) restores the default
+  if (err != hipSuccess) return fail(NADMM_ERR_HIP, "autotune: %s", hipGetErrorString(err));
+  if (rows_out) *rows_out = xline_rows(g);
+  return NADMM_OK;
+}
+
 nadmm_status nadmm_workspace_size_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpoint,
                                        size_t* bytes) {
   if (!bytes) return fail(NADMM_ERR_INVALID_ARG, "bytes is NULL");

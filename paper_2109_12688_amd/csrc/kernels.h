@@ -12,8 +12,12 @@ struct Geo {
   int V;  // nx * ny * nz
 };
 
-// Rows of the y axis handled by one x-line workgroup (even, divides ny).
-int xline_rows(int ny);
+// Rows of the y axis handled by one x-line workgroup (even, divides ny):
+// the value set for these sizes by xline_rows_set (the autotuner; 0 clears
+// it), else a default.  Results do not depend on it.
+int xline_rows(const Geo& g);
+int xline_rows_default(int ny);
+void xline_rows_set(const Geo& g, int rows);
 // Threads of the x-line passes and of the y-z plane pass for these sizes.
 int xline_threads(const Geo& g);
 int plane_threads(const Geo& g);

@@ -26,6 +26,9 @@
 // the same lines without leaving the chip.
 #include <float.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "kernels.h"
@@ -59,10 +62,30 @@ static inline int xline_stride(int nx) { return xl_pad_host(nx) + XL_EXTRA; }
 // ---------------------------------------------------------------------------
 // host-side geometry helpers
 // ---------------------------------------------------------------------------
-int xline_rows(int ny) {
+// Rows per x-line workgroup: the tuned value for these sizes when one was
+// set (xline_rows_set, from the autotuner), else the largest even divisor of
+// ny up to XL_MAX_ROWS.
+static std::mutex g_rows_mu;
+static std::map<std::tuple<int, int, int>, int> g_rows;
+
+int xline_rows_default(int ny) {
   for (int yb = XL_MAX_ROWS; yb >= 2; yb -= 2)
     if (ny % yb == 0) return yb;
   return 2;
+}
+
+int xline_rows(const Geo& g) {
+  std::lock_guard<std::mutex> lk(g_rows_mu);
+  auto it = g_rows.find(std::make_tuple(g.nx, g.ny, g.nz));
+  return it != g_rows.end() ? it->second : xline_rows_default(g.ny);
+}
+
+void xline_rows_set(const Geo& g, int rows) {
+  std::lock_guard<std::mutex> lk(g_rows_mu);
+  if (rows > 0)
+    g_rows[std::make_tuple(g.nx, g.ny, g.nz)] = rows;
+  else
+    g_rows.erase(std::make_tuple(g.nx, g.ny, g.nz));
 }
 
 static int round_up(int a, int b) { return (a + b - 1) / b * b; }
@@ -74,7 +97,7 @@ size_t plane_lds_bytes(const Geo& g, int rs) {
 }
 
 int xline_threads(const Geo& g) {
-  const int elems = 3 * (xline_rows(g.ny) / 2) * g.nx;
+  const int elems = 3 * (xline_rows(g) / 2) * g.nx;
   int t = round_up((elems + 7) / 8, 64);
   if (t > 1024) t = 1024;
   if (t < 64) t = 64;
@@ -186,7 +209,7 @@ static bool split_shape_ok(const Geo& g);
 
 bool launch_shape_ok(const Geo& g) {
   if (g.nx % 4 || g.ny % 2) return false;
-  const int yb = xline_rows(g.ny), xt = xline_threads(g), pt = plane_threads(g);
+  const int yb = xline_rows(g), xt = xline_threads(g), pt = plane_threads(g);
   const FftPlan px = make_plan(g.nx), py = make_plan(g.ny), pz = make_plan(g.nz);
   if (px.nstages < 1 || py.nstages < 1 || pz.nstages < 1) return false;
   const bool fft_a = 3 * (yb / 2) * g.nx <= kEpt * xt;       // x-line FFT elements per thread
@@ -205,7 +228,7 @@ bool launch_shape_ok(const Geo& g) {
 }
 
 XDivs make_xdivs(const Geo& g) {
-  const int yb = xline_rows(g.ny);
+  const int yb = xline_rows(g);
   XDivs d;
   d.q4 = make_fastdiv(g.nx / 4);
   d.yb = make_fastdiv(yb);
@@ -570,13 +593,13 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
 }
 
 static size_t pass_a_lds(const Geo& g) {
-  const int yb = xline_rows(g.ny);
+  const int yb = xline_rows(g);
   return sizeof(float2) * ((size_t)g.nx + (size_t)3 * (yb / 2) * xline_stride(g.nx));
 }
 
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
                          const float* s2, float gamma, float2* X, hipStream_t st, int batch) {
-  const int yb = xline_rows(g.ny);
+  const int yb = xline_rows(g);
   const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads(g));
   const size_t lds = pass_a_lds(g);
   const XDivs xd = make_xdivs(g);
@@ -1290,7 +1313,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
 
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
                          const PassCArgs& a, hipStream_t st, int batch) {
-  const int yb = xline_rows(g.ny);
+  const int yb = xline_rows(g);
   const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads(g));
   const size_t lds = pass_a_lds(g);
   const XDivs xd = make_xdivs(g);

@@ -52,3 +52,50 @@ def test_batch_rejects_bad_batch(api):
     from paper_2109_12688_amd import _lib
     with pytest.raises(Exception):
         api.workspace_batch((16, 8, 8), 0)
+
+
+def test_autotune_keeps_results(api):
+    d = (32, 24, 16)
+    f = gpu(synth.random_volume(d, seed=110, smooth_kmax=3))
+    m = gpu(synth.random_volume(d, seed=111, smooth_kmax=3))
+    args = (0.01, 0.1, 2, 2, 5)
+    before = api.register(f, m, *args)
+    rows = api.autotune(f.shape, 0.01, 0.1, 2)
+    assert rows > 0 and d[1] % rows == 0 and rows % 2 == 0
+    after = api.register(f, m, *args)
+    assert torch.equal(before["disp"], after["disp"])
+    assert torch.equal(before["warped"], after["warped"])
+
+
+def test_graph_replay_matches_eager(api):
+    """A registration captured in a graph: several replays, with eager work
+    and synchronisations between them, each equal to the eager result."""
+    d = (32, 24, 16)
+    f = gpu(synth.random_volume(d, seed=120, smooth_kmax=3))
+    m = gpu(synth.random_volume(d, seed=121, smooth_kmax=3))
+    args = (0.01, 0.1, 2, 3, 6)
+    shp = tuple(f.shape)
+    ws = api.workspace(shp)
+    out = {"disp": torch.empty((3,) + shp, device="cuda"), "warped": torch.empty(shp, device="cuda")}
+    api.register(f, m, *args, ws=ws, out=out)
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in out.items()}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        api.register(f, m, *args, ws=ws, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        api.register(f, m, *args, ws=ws, out=out)
+    other = gpu(synth.random_volume(d, seed=122, smooth_kmax=3))
+    for _ in range(3):
+        out["disp"].zero_()
+        out["warped"].zero_()
+        api.register(other, m, *args)  # eager work between the replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out["disp"], eager["disp"])
+        assert torch.equal(out["warped"], eager["warped"])
