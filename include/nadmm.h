@@ -141,6 +141,30 @@ nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_param
                                   const float* init_disp, float* disp, float* warped,
                                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* Multi-resolution registration (Sec. 4: the three-level pyramid of the
+ * first hyper-parameter version caps the ADMM iterations at 10, 5, 5 and the
+ * warpings at 10, 10, 5, coarsest level first).  Level l of `levels` (1..4,
+ * l = 0 the coarsest) has every dimension divided by 2^(levels-1-l), which
+ * must divide it and give supported sizes; its images are 2x2x2 averages of
+ * the next finer level's.  Each level runs nadmm_register with
+ * outer[l] warpings of iters[l] iterations (p->outer / p->iters are
+ * ignored; lambda, theta, n and the data term are the same at every level),
+ * starting from the previous level's displacement carried to its grid:
+ * u_fine(x) = 2 u_coarse((x - 1/2) / 2), periodic trilinear (coarse voxel i
+ * covers fine voxels 2i and 2i + 1).  The finest level's displacement goes
+ * to disp, its warped image to warped (may be NULL).  Workspace:
+ * nadmm_workspace_size_pyramid bytes. */
+typedef struct {
+  int32_t levels;
+  int32_t outer[4];
+  int32_t iters[4];
+} nadmm_pyramid;
+nadmm_status nadmm_workspace_size_pyramid(nadmm_dims d, const nadmm_pyramid* pyr, size_t* bytes);
+nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const nadmm_pyramid* pyr,
+                                    const float* fixed, const float* moving, float* disp,
+                                    float* warped, void* workspace, size_t workspace_bytes,
+                                    void* stream);
+
 /* Tile autotuner: times the fused x-line pass of the iteration for every
  * admissible number of y rows per workgroup (even divisors of ny up to 32
  * that fit the kernels' per-thread bounds), `reps` = 20 launches each

@@ -472,3 +472,65 @@ def ssd_one_warping_grad(fixed: np.ndarray, moving: np.ndarray, lam: float, thet
         d_iw -= central_diff(gJ[c], ax)
     d_moving += d_iw
     return loss, d_moving, d_lam
+
+
+# ---------------------------------------------------------------------------
+# Three-level pyramid (Sec. 4, first hyper-parameter version)
+# ---------------------------------------------------------------------------
+# The paper caps the ADMM iterations at 10, 5, 5 and the warpings at 10, 10,
+# 5 over three pyramid levels (coarse to fine) and says nothing more.
+# Readings: each coarser level halves every dimension by 2x2x2 averaging of
+# the images; a level starts from the previous level's displacement carried
+# to its grid (coarse voxel i covers fine voxels 2i and 2i + 1, so the
+# coarse sample position of fine voxel x is (x - 1/2) / 2, and displacements
+# in voxels double); lambda, theta and n are the same at every level.
+
+def downsample2(f: np.ndarray) -> np.ndarray:
+    """2x2x2 average of a (nz, ny, nx) volume with even dimensions."""
+    nz, ny, nx = f.shape
+    return f.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(1, 3, 5))
+
+
+def sample_periodic(f: np.ndarray, px: np.ndarray, py: np.ndarray, pz: np.ndarray) -> np.ndarray:
+    """Periodic trilinear value of the (nz, ny, nx) grid function f at the
+    points (px, py, pz) (grid coordinates, any shape)."""
+    nz, ny, nx = f.shape
+    fx, fy, fz = np.floor(px), np.floor(py), np.floor(pz)
+    tx, ty, tz = px - fx, py - fy, pz - fz
+    x0 = np.mod(fx.astype(np.int64), nx)
+    y0 = np.mod(fy.astype(np.int64), ny)
+    z0 = np.mod(fz.astype(np.int64), nz)
+    x1, y1, z1 = np.mod(x0 + 1, nx), np.mod(y0 + 1, ny), np.mod(z0 + 1, nz)
+    return ((1 - tz) * ((1 - ty) * ((1 - tx) * f[z0, y0, x0] + tx * f[z0, y0, x1])
+                        + ty * ((1 - tx) * f[z0, y1, x0] + tx * f[z0, y1, x1]))
+            + tz * ((1 - ty) * ((1 - tx) * f[z1, y0, x0] + tx * f[z1, y0, x1])
+                    + ty * ((1 - tx) * f[z1, y1, x0] + tx * f[z1, y1, x1])))
+
+
+def upsample2_disp(u: np.ndarray) -> np.ndarray:
+    """A coarse displacement (3, nz, ny, nx) carried to the grid twice as
+    fine: u_f(x) = 2 u_c((x - 1/2) / 2), periodic trilinear."""
+    nz, ny, nx = u.shape[1:]
+    zz, yy, xx = np.meshgrid(np.arange(2 * nz), np.arange(2 * ny), np.arange(2 * nx), indexing="ij")
+    px, py, pz = (xx - 0.5) / 2.0, (yy - 0.5) / 2.0, (zz - 0.5) / 2.0
+    return np.stack([2.0 * sample_periodic(u[c], px, py, pz) for c in range(3)])
+
+
+def pyramid_register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float, order: int,
+                     outer=(10, 10, 5), iters=(10, 5, 5), data_term: int = 2) -> RegisterResult:
+    """`register` over len(outer) levels, coarsest first, each level starting
+    from the previous level's displacement carried to its grid."""
+    levels = len(outer)
+    fs = [np.asarray(fixed, np.float64)]
+    ms = [np.asarray(moving, np.float64)]
+    for _ in range(levels - 1):
+        fs.insert(0, downsample2(fs[0]))
+        ms.insert(0, downsample2(ms[0]))
+    u = None
+    res = None
+    for lv in range(levels):
+        init = None if u is None else upsample2_disp(u)
+        res = register(fs[lv], ms[lv], lam, theta, order, outer[lv], iters[lv], data_term=data_term,
+                       init_disp=init)
+        u = res.disp
+    return res

@@ -28,6 +28,10 @@ class Params(ctypes.Structure):
                 ("eps", ctypes.c_double), ("outer", ctypes.c_int32), ("iters", ctypes.c_int32)]
 
 
+class Pyramid(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("outer", ctypes.c_int32 * 4), ("iters", ctypes.c_int32 * 4)]
+
+
 class NadmmError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str):
         self.status = status
@@ -53,6 +57,10 @@ _SIGS = {
                        ctypes.c_int),
     "nadmm_autotune": ([Dims, ctypes.c_int32, ctypes.POINTER(Params), _P, ctypes.c_size_t, _P,
                         ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "nadmm_workspace_size_pyramid": ([Dims, ctypes.POINTER(Pyramid), ctypes.POINTER(ctypes.c_size_t)],
+                                     ctypes.c_int),
+    "nadmm_register_pyramid": ([Dims, ctypes.POINTER(Params), ctypes.POINTER(Pyramid), _P, _P, _P, _P, _P,
+                                ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_admm": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_fourier_solve": ([Dims, ctypes.POINTER(Params), _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_warp": ([Dims, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),

@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import Dims, Params
+from ._lib import Dims, Params, Pyramid
 
 
 def _stream() -> ctypes.c_void_p:
@@ -172,6 +172,40 @@ def ssd_grad(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float
               _ptr(moving), _ptr(loss), _ptr(dmov), _ptr(dlam), _ptr(ws), ctypes.c_size_t(ws.numel()),
               _stream())
     return loss, dmov, dlam
+
+
+def pyramid(outer=(10, 10, 5), iters=(10, 5, 5)) -> Pyramid:
+    if len(outer) != len(iters) or not 1 <= len(outer) <= 4:
+        raise ValueError("outer and iters need one entry per level (1 to 4 levels)")
+    py = Pyramid()
+    py.levels = len(outer)
+    for i, (o, k) in enumerate(zip(outer, iters)):
+        py.outer[i] = int(o)
+        py.iters[i] = int(k)
+    return py
+
+
+def register_pyramid(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
+                     outer=(10, 10, 5), iters=(10, 5, 5), data_term: int = 2, eps: float = 1e-8,
+                     ws: torch.Tensor | None = None) -> dict:
+    """Multi-resolution registration, coarsest level first (see
+    nadmm_register_pyramid); the defaults are the paper's caps of its first
+    hyper-parameter version.  Returns 'disp' and 'warped' at full size."""
+    _check(fixed, "fixed")
+    shp = tuple(fixed.shape)
+    _check(moving, "moving", shp)
+    py = pyramid(outer, iters)
+    if ws is None:
+        n = ctypes.c_size_t(0)
+        _lib.call("nadmm_workspace_size_pyramid", dims_of(shp), ctypes.byref(py), ctypes.byref(n))
+        ws = torch.empty(int(n.value), dtype=torch.uint8, device=fixed.device)
+    _check(ws, "workspace", dtype=torch.uint8)
+    disp = torch.empty((3,) + shp, dtype=torch.float32, device=fixed.device)
+    warped = torch.empty(shp, dtype=torch.float32, device=fixed.device)
+    p = params(lam, theta, order, 1, 1, data_term, eps)
+    _lib.call("nadmm_register_pyramid", dims_of(shp), ctypes.byref(p), ctypes.byref(py), _ptr(fixed),
+              _ptr(moving), _ptr(disp), _ptr(warped), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    return {"disp": disp, "warped": warped}
 
 
 def autotune(vol_shape, lam: float, theta: float, order: int, batch: int = 1,

@@ -385,6 +385,55 @@ nadmm_status check_grad_args(const nadmm_params* p, int32_t checkpoint) {
   return NADMM_OK;
 }
 
+// ---- pyramid ---------------------------------------------------------------
+// Workspace of nadmm_register_pyramid: the registration workspace of the
+// finest level (every level's fits in it), then for each coarser level its
+// two images and its displacement, and one buffer for the displacement
+// carried to the next level (the finest size).
+struct PyrLayout {
+  size_t reg, img[4], disp[4], carry, total;
+};
+
+nadmm_dims level_dims(const nadmm_dims& d, int levels, int l) {
+  const int sh = levels - 1 - l;  // l = 0 is the coarsest
+  return nadmm_dims{d.nx >> sh, d.ny >> sh, d.nz >> sh};
+}
+
+PyrLayout pyr_layout(const nadmm_dims& d, int levels) {
+  PyrLayout L{};
+  size_t o = 0;
+  L.reg = o;
+  o += layout(d).total;
+  for (int l = 0; l + 1 < levels; ++l) {
+    const nadmm_dims dl = level_dims(d, levels, l);
+    const size_t V = (size_t)dl.nx * dl.ny * dl.nz;
+    L.img[l] = o;
+    o += align256(2 * V * sizeof(float));
+    L.disp[l] = o;
+    o += align256(3 * V * sizeof(float));
+  }
+  L.carry = o;
+  o += align256(3 * (size_t)d.nx * d.ny * d.nz * sizeof(float));
+  L.total = o;
+  return L;
+}
+
+nadmm_status check_pyramid(const nadmm_dims& d, const nadmm_pyramid* pyr) {
+  if (!pyr) return fail(NADMM_ERR_INVALID_ARG, "pyramid is NULL");
+  if (pyr->levels < 1 || pyr->levels > 4)
+    return fail(NADMM_ERR_INVALID_ARG, "levels must be in [1, 4] (got %d)", pyr->levels);
+  const int m = 1 << (pyr->levels - 1);
+  if (d.nx % m || d.ny % m || d.nz % m)
+    return fail(NADMM_ERR_UNSUPPORTED_SIZE, "dims (%d, %d, %d) must be divisible by %d for %d levels",
+                d.nx, d.ny, d.nz, m, pyr->levels);
+  for (int l = 0; l < pyr->levels; ++l) {
+    CHECK(check_dims(level_dims(d, pyr->levels, l)));
+    if (pyr->outer[l] < 0 || pyr->outer[l] > 100000 || pyr->iters[l] < 1 || pyr->iters[l] > 100000)
+      return fail(NADMM_ERR_INVALID_ARG, "level %d: outer in [0, 100000], iters in [1, 100000]", l);
+  }
+  return NADMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -504,6 +553,69 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
   xline_rows_set(g, best);  // 0 (nothing timed) restores the default
   if (err != hipSuccess) return fail(NADMM_ERR_HIP, "autotune: %s", hipGetErrorString(err));
   if (rows_out) *rows_out = xline_rows(g);
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_workspace_size_pyramid(nadmm_dims d, const nadmm_pyramid* pyr, size_t* bytes) {
+  if (!bytes) return fail(NADMM_ERR_INVALID_ARG, "bytes is NULL");
+  CHECK(check_dims(d));
+  CHECK(check_pyramid(d, pyr));
+  *bytes = pyr_layout(d, pyr->levels).total;
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const nadmm_pyramid* pyr,
+                                    const float* fixed, const float* moving, float* disp,
+                                    float* warped, void* workspace, size_t workspace_bytes,
+                                    void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_pyramid(d, pyr));
+  CHECK(check_params(p, false));
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(warped, "warped", true));
+  CHECK(check_ptr(workspace, "workspace", false));
+  const int L = pyr->levels;
+  const PyrLayout PL = pyr_layout(d, L);
+  if (workspace_bytes < PL.total)
+    return fail(NADMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                workspace_bytes, PL.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // images of every level, finest first down to the coarsest
+  const float* F[4];
+  const float* M[4];
+  F[L - 1] = fixed;
+  M[L - 1] = moving;
+  for (int l = L - 2; l >= 0; --l) {
+    const nadmm_dims dl = level_dims(d, L, l);
+    const Geo gl = geo(dl);
+    float* fl = at<float>(workspace, PL.img[l]);
+    float* ml = fl + gl.V;
+    HIP_TRY(launch_downsample2(gl, F[l + 1], fl, st));
+    HIP_TRY(launch_downsample2(gl, M[l + 1], ml, st));
+    F[l] = fl;
+    M[l] = ml;
+  }
+  const size_t reg_bytes = PL.img[0] - PL.reg;  // == layout(d).total (rounded)
+  const float* u_prev = nullptr;
+  for (int l = 0; l < L; ++l) {
+    const nadmm_dims dl = level_dims(d, L, l);
+    const float* init = nullptr;
+    if (u_prev) {
+      float* carry = at<float>(workspace, PL.carry);
+      HIP_TRY(launch_upsample2_disp(geo(dl), u_prev, carry, st));
+      init = carry;
+    }
+    float* out = (l == L - 1) ? disp : at<float>(workspace, PL.disp[l]);
+    nadmm_params pl = *p;
+    pl.outer = pyr->outer[l];
+    pl.iters = pyr->iters[l];
+    CHECK(register_impl(dl, &pl, F[l], M[l], init, out, l == L - 1 ? warped : nullptr, nullptr,
+                        at<char>(workspace, PL.reg), L > 1 ? reg_bytes : workspace_bytes, stream,
+                        1));
+    u_prev = out;
+  }
   return NADMM_OK;
 }
 

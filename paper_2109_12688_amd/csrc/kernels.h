@@ -132,6 +132,10 @@ hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda,
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
                          const PassCArgs& a, hipStream_t st, int batch = 1);
 hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out, hipStream_t st);
+// Pyramid resampling: coarse (geometry gc) = 2x2x2 average of fine;
+// uf (geometry gf) = 2 uc((x - 1/2) / 2), periodic trilinear, per component.
+hipError_t launch_downsample2(const Geo& gc, const float* fine, float* coarse, hipStream_t st);
+hipError_t launch_upsample2_disp(const Geo& gf, const float* uc, float* uf, hipStream_t st);
 
 // Differentiated warping (adjoint.hip).  Fields are float32 vector fields
 // (3V) unless noted; r, gr, resid, d_img are scalar volumes.

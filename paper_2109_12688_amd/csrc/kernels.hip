@@ -408,6 +408,60 @@ hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* o
 }
 
 // ---------------------------------------------------------------------------
+// pyramid resampling (coarse voxel i covers fine voxels 2i and 2i + 1)
+// ---------------------------------------------------------------------------
+// coarse = 2x2x2 average of fine; gc is the coarse geometry
+__global__ void k_downsample2(Geo gc, const float* __restrict__ fine, float* __restrict__ coarse) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= gc.V) return;
+  const int x = i % gc.nx, y = (i / gc.nx) % gc.ny, z = i / (gc.nx * gc.ny);
+  const int fx = 2 * gc.nx, fy = 2 * gc.ny;
+  const float* p = fine + ((size_t)(2 * z) * fy + 2 * y) * fx + 2 * x;
+  const size_t sy = fx, sz = (size_t)fx * fy;
+  const float a = (p[0] + p[1]) + (p[sy] + p[sy + 1]);
+  const float b = (p[sz] + p[sz + 1]) + (p[sz + sy] + p[sz + sy + 1]);
+  coarse[i] = (a + b) * 0.125f;
+}
+
+// uf(x) = 2 uc((x - 1/2) / 2), periodic trilinear; gf is the fine geometry
+__global__ void k_upsample2_disp(Geo gf, const float* __restrict__ uc, float* __restrict__ uf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= gf.V) return;
+  const int x = i % gf.nx, y = (i / gf.nx) % gf.ny, z = i / (gf.nx * gf.ny);
+  const Geo gc{gf.nx / 2, gf.ny / 2, gf.nz / 2, gf.V / 8};
+  auto axis = [](int xf, int nc, int& i0, int& i1, float& t) {
+    const float p = ((float)xf - 0.5f) * 0.5f;
+    const float f = floorf(p);
+    t = p - f;
+    i0 = (int)f;
+    if (i0 < 0) i0 += nc;
+    i1 = (i0 + 1 == nc) ? 0 : i0 + 1;
+  };
+  int x0, x1, y0, y1, z0, z1;
+  Tap t;
+  axis(x, gc.nx, x0, x1, t.tx);
+  axis(y, gc.ny, y0, y1, t.ty);
+  axis(z, gc.nz, z0, z1, t.tz);
+  const int r00 = (z0 * gc.ny + y0) * gc.nx, r01 = (z0 * gc.ny + y1) * gc.nx;
+  const int r10 = (z1 * gc.ny + y0) * gc.nx, r11 = (z1 * gc.ny + y1) * gc.nx;
+  t.o000 = r00 + x0; t.o100 = r00 + x1;
+  t.o010 = r01 + x0; t.o110 = r01 + x1;
+  t.o001 = r10 + x0; t.o101 = r10 + x1;
+  t.o011 = r11 + x0; t.o111 = r11 + x1;
+  for (int c = 0; c < 3; ++c) uf[(size_t)c * gf.V + i] = 2.0f * sample(uc + (size_t)c * gc.V, t);
+}
+
+hipError_t launch_downsample2(const Geo& gc, const float* fine, float* coarse, hipStream_t st) {
+  hipLaunchKernelGGL(k_downsample2, dim3((gc.V + 255) / 256), dim3(256), 0, st, gc, fine, coarse);
+  return hipGetLastError();
+}
+
+hipError_t launch_upsample2_disp(const Geo& gf, const float* uc, float* uf, hipStream_t st) {
+  hipLaunchKernelGGL(k_upsample2_disp, dim3((gf.V + 255) / 256), dim3(256), 0, st, gf, uc, uf);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // transform tables (float64, rounded once)
 // ---------------------------------------------------------------------------
 static size_t a256(size_t b) { return (b + 255) / 256 * 256; }

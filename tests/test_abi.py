@@ -138,3 +138,21 @@ def test_python_binding_rejects_cpu_tensors():
     x = torch.zeros(4, 4, 8)
     with pytest.raises(ValueError):
         api.warp(x, torch.zeros(3, 4, 4, 8))
+
+
+def test_pyramid_argument_checks(lib):
+    from paper_2109_12688_amd._lib import Pyramid
+    n = ctypes.c_size_t(0)
+    py = Pyramid()
+    py.levels = 3
+    for i, (o, k) in enumerate(((10, 10), (10, 5), (5, 5))):
+        py.outer[i], py.iters[i] = o, k
+    assert lib.nadmm_workspace_size_pyramid(Dims(128, 128, 96), ctypes.byref(py), ctypes.byref(n)) == 0
+    assert n.value > 14 * 4 * 128 * 128 * 96
+    # 100 is not divisible by 4 for three levels; 4 levels of 24^3 reach 3^3
+    assert lib.nadmm_workspace_size_pyramid(Dims(100, 128, 96), ctypes.byref(py), ctypes.byref(n)) == 2
+    py.levels = 4
+    py.outer[3], py.iters[3] = 1, 1
+    assert lib.nadmm_workspace_size_pyramid(Dims(24, 24, 24), ctypes.byref(py), ctypes.byref(n)) == 2
+    py.levels = 5
+    assert lib.nadmm_workspace_size_pyramid(Dims(64, 64, 64), ctypes.byref(py), ctypes.byref(n)) == 1

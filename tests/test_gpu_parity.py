@@ -207,3 +207,20 @@ def test_determinism(api):
     a = api.register(gpu(pair.fixed), gpu(pair.moving), 0.01, 0.1, 2, 2, 6)
     b = api.register(gpu(pair.fixed), gpu(pair.moving), 0.01, 0.1, 2, 2, 6)
     assert torch.equal(a["disp"], b["disp"]) and torch.equal(a["warped"], b["warped"])
+
+
+def test_pyramid_vs_oracle(api):
+    """Three levels (16x16x12, 32x32x24, 64x64x48) with the paper's caps of
+    its first hyper-parameter version: warpings 10, 10, 5 and iterations
+    10, 5, 5."""
+    d = (64, 64, 48)
+    f = synth.random_volume(d, seed=130, smooth_kmax=3)
+    m = synth.random_volume(d, seed=131, smooth_kmax=3)
+    res = api.register_pyramid(gpu(f), gpu(m), 0.01, 0.1, 2)
+    ref = O.pyramid_register(f64(f), f64(m), 0.01, 0.1, 2, outer=(10, 10, 5), iters=(10, 5, 5))
+    assert np.abs(host(res["disp"]) - ref.disp).max() < 1e-3
+    assert np.abs(host(res["warped"]) - ref.warped).max() < 1e-4
+    # one level is a plain registration
+    one = api.register_pyramid(gpu(f), gpu(m), 0.01, 0.1, 2, outer=(2,), iters=(3,))
+    plain = api.register(gpu(f), gpu(m), 0.01, 0.1, 2, 2, 3)
+    assert torch.equal(one["disp"], plain["disp"])

@@ -518,3 +518,48 @@ def test_p19_one_warping_gradient_matches_differences(order, iters):
     fd = (O.ssd_one_warping(f, m, lam + h, theta, order, iters)
           - O.ssd_one_warping(f, m, lam - h, theta, order, iters)) / (2 * h)
     assert abs(fd - gl) < 1e-6 * max(1.0, abs(fd)), (fd, gl)
+
+
+# ---------------------------------------------------------------------------
+# P20: the pyramid's resampling
+# ---------------------------------------------------------------------------
+def test_p20_pyramid_resampling():
+    rng = np.random.default_rng(200)
+    # averaging: block-constant volumes come back exactly, means are kept
+    blocks = rng.standard_normal((3, 4, 5))
+    f = np.repeat(np.repeat(np.repeat(blocks, 2, 0), 2, 1), 2, 2)
+    assert np.array_equal(O.downsample2(f), blocks)
+    g = rng.standard_normal((6, 8, 10))
+    assert abs(O.downsample2(g).mean() - g.mean()) < 1e-14
+    # the general sampler equals the library's periodic linear interpolation
+    c = rng.standard_normal((5, 6, 7))
+    pts = [rng.uniform(-8, 16, 50) for _ in range(3)]
+    ref = ndimage.map_coordinates(c, np.stack([pts[2], pts[1], pts[0]]), order=1, mode="grid-wrap")
+    assert np.abs(O.sample_periodic(c, *pts) - ref).max() < 1e-12
+    # carrying a displacement: constants double
+    const = np.stack([np.full((4, 5, 6), v) for v in (0.5, -1.25, 2.0)])
+    up = O.upsample2_disp(const)
+    assert up.shape == (3, 8, 10, 12)
+    assert np.allclose(up[0], 1.0) and np.allclose(up[1], -2.5) and np.allclose(up[2], 4.0)
+    # a profile along x only: fine voxel 2i samples coarse position i - 1/4 and
+    # 2i + 1 samples i + 1/4, so u_f(2i) = 2 (u(i-1)/4 + 3 u(i)/4) and
+    # u_f(2i+1) = 2 (3 u(i)/4 + u(i+1)/4), indices periodic
+    prof = rng.standard_normal(6)
+    u = np.zeros((3, 4, 5, 6))
+    u[1] = prof[None, None, :]
+    upu = O.upsample2_disp(u)[1, 0, 0]
+    prev, nxt = np.roll(prof, 1), np.roll(prof, -1)
+    assert np.abs(upu[0::2] - 2.0 * (0.25 * prev + 0.75 * prof)).max() < 1e-12
+    assert np.abs(upu[1::2] - 2.0 * (0.75 * prof + 0.25 * nxt)).max() < 1e-12
+
+
+def test_p20_pyramid_identity_and_levels():
+    d = (32, 24, 16)
+    img = synth.random_volume(d, seed=201, smooth_kmax=2).astype(np.float64)
+    res = O.pyramid_register(img, img, 0.01, 0.1, 2, outer=(2, 2, 1), iters=(3, 2, 2))
+    assert np.array_equal(res.disp, np.zeros_like(res.disp))
+    # one level is a plain registration
+    f = synth.random_volume(d, seed=202, smooth_kmax=2).astype(np.float64)
+    one = O.pyramid_register(f, img, 0.01, 0.1, 2, outer=(2,), iters=(3,))
+    ref = O.register(f, img, 0.01, 0.1, 2, 2, 3)
+    assert np.array_equal(one.disp, ref.disp)
