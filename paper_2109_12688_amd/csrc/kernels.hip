@@ -763,6 +763,12 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   // the x transform of pass A already carries 1 / nx of the inverse's 1 / V
   const float inv_v = 1.0f / (float)(ny * nz);
   const int nlw_y = 64 / (NY ? PlansCT<NY ? NY : 32, NZ ? NZ : 32>::PY.L : py0.L);
+  // Compile-time sizes: the host launches at least ceil(nz / nlw_y) and
+  // ceil(ny / nlw_z) wavefronts when both are <= 16, so every wavefront owns at
+  // most one group of rows and one group of columns (no loop over groups).
+  using PCT = PlansCT<NY ? NY : 32, NZ ? NZ : 32>;
+  constexpr int kNlwY = 64 / PCT::PY.L, kNlwZ = 64 / PCT::PZ.L;
+  constexpr bool ONE_PASS = NY > 0 && (NZ + kNlwY - 1) / kNlwY <= 16 && (NY + kNlwZ - 1) / kNlwZ <= 16;
 
   // Rows of the y transform are owned by wavefronts: lines [l0, l0 + nlw_y)
   // with l0 = wave * nlw_y (+ multiples of nwaves * nlw_y).  Issue the loads
@@ -783,7 +789,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
       const int idx = b0 + lane + it * 64;
       if (idx < items) {
         const int i = 2 * idx;
-        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;  // yy even
+        const int zz = NY ? i / NY : (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;  // yy even
         float2* d = buf + (l0 + zz) * rs + lpad<4>(yy);
         d[0] = make_float2(v[it].x, v[it].y);
         d[1] = make_float2(v[it].z, v[it].w);
@@ -838,7 +844,10 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   __syncthreads();
 
   // --- along y ---------------------------------------------------------------
-  {
+  if constexpr (ONE_PASS) {
+    const int l = wave * kNlwY + lane % kNlwY;
+    if (l < nz) pol.template y_all<false>(buf + l * rs, twy, lane / kNlwY);
+  } else {
     const int nlw = nlw_y, li = lane % nlw, tl = lane / nlw;
     for (int l0 = wave * nlw; l0 < nz; l0 += nwaves * nlw) {
       if (l0 != wave * nlw) {  // further row groups of this wavefront
@@ -866,6 +875,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
         const SpectralMult mult{sz, sx + sy[q], lambda, theta, inv_v, order, DERIV ? 1 : 0};
         pol.z_fused(buf + lpad<4>(q), twz, tl, rs, mult);
       }
+      if constexpr (ONE_PASS) break;
     }
   }
   __syncthreads();
@@ -875,13 +885,15 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
     const int nlw = nlw_y, li = lane % nlw, tl = lane / nlw;
     float4* out4 = reinterpret_cast<float4*>(plane);
     for (int l0 = wave * nlw; l0 < nz; l0 += nwaves * nlw) {
+      if constexpr (ONE_PASS)
+        if (l0 != wave * nlw) break;
       const int l = l0 + li;
       if (l < nz) pol.template y_all<true>(buf + l * rs, twy, tl);
       wave_lds_fence();
       const int items = (nz - l0 < nlw ? nz - l0 : nlw) * (ny / 2);
       for (int idx = lane; idx < items; idx += 64) {
         const int i = 2 * idx;
-        const int zz = (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
+        const int zz = NY ? i / NY : (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
         const float2* sp = buf + (l0 + zz) * rs + lpad<4>(yy);
         const float2 a = sp[0], b = sp[1];
         out4[l0 * (ny / 2) + idx] = make_float4(a.x, a.y, b.x, b.y);
