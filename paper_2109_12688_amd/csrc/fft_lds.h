@@ -626,6 +626,26 @@ struct SpectralMult {
     const float rd = __builtin_amdgcn_rcpf(theta + lambda * kn);
     return deriv ? -theta * scale * kn * rd * rd : theta * scale * rd;
   }
+  // The multipliers of elements j, j + ns, ..., j + (R-1) ns at once (the same
+  // operations per element as operator()): all symbol reads are issued
+  // together and the power is one uniform loop over the R elements.
+  template <int R>
+  __device__ __forceinline__ void fill(int j, int ns, float* m) const {
+    float k0[R], kn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) k0[r] = kq + ks[j + r * ns];
+#pragma unroll
+    for (int r = 0; r < R; ++r) kn[r] = k0[r];
+    for (int i = 1; i < order; ++i) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) kn[r] *= k0[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float rd = __builtin_amdgcn_rcpf(theta + lambda * kn[r]);
+      m[r] = deriv ? -theta * scale * kn[r] * rd * rd : theta * scale * rd;
+    }
+  }
 };
 
 template <int R, int EPT, int PADSH>
@@ -645,8 +665,10 @@ __device__ __forceinline__ void team_fused(float2* line, const float2* tw, const
       const int j = tl + m * L;
       float2* w = v + m * R;
       team_compute<R, false>(tw, sf, j, w);
+      float mr[R];
+      mult.template fill<R>(j, sf.Ns, mr);
 #pragma unroll
-      for (int r = 0; r < R; ++r) w[r] = cscale(w[r], mult(j + r * sf.Ns));
+      for (int r = 0; r < R; ++r) w[r] = cscale(w[r], mr[r]);
       Dft<R, true>::run(w);  // first inverse stage: all twiddles are 1
       team_store<R, PADSH>(line, es, si, j, w);
     }

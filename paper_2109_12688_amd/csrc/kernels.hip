@@ -142,8 +142,8 @@ TeamPlan reverse_team_plan(const TeamPlan& p) { return reverse_team_plan_ce(p); 
 // LDS reads of both phases (y rows and z columns) of one wavefront, counting
 // lanes of each group of 16 that share a bank pair (32 banks of 4 bytes,
 // 16 lanes per cycle for 8-byte accesses), subject to fitting in LDS.
-static int ypad(int y) { return y + (y >> 4); }
-static int plane_conflicts(const TeamPlan& p, int nlines, int rs, bool rows) {
+constexpr int ypad(int y) { return y + (y >> 4); }
+constexpr int plane_conflicts(const TeamPlan& p, int nlines, int rs, bool rows) {
   const int nlw = 64 / p.L;
   int score = 0;
   for (int grp = 0; grp < 4; ++grp) {
@@ -162,20 +162,26 @@ static int plane_conflicts(const TeamPlan& p, int nlines, int rs, bool rows) {
   return score;
 }
 
-int plane_row_stride(const Geo& g) {
-  const TeamPlan py = plane_plan_y(g), pz = plane_plan_z(g);
-  const int base = ypad(g.ny - 1) + 1;
+// Evaluated at compile time by the fixed-size plane kernels (which then
+// address LDS with constant offsets) and at run time by the host, so both
+// sides agree on the stride.
+constexpr int plane_row_stride_ce(int ny, int nz, const TeamPlan& py, const TeamPlan& pz) {
+  const int base = ypad(ny - 1) + 1;
   int best = base, best_score = 1 << 30;
   for (int e = 0; e < 16; ++e) {
     const int rs = base + e;
-    if (plane_lds_bytes(g, rs) > kMaxLds) break;
-    const int sc = plane_conflicts(py, g.nz, rs, true) + plane_conflicts(pz, g.ny, rs, false);
+    if (8 * (ny + nz) + 4 * (ny + nz + 1) + 8 * nz * rs > kMaxLds) break;
+    const int sc = plane_conflicts(py, nz, rs, true) + plane_conflicts(pz, ny, rs, false);
     if (sc < best_score) {
       best_score = sc;
       best = rs;
     }
   }
   return best;
+}
+
+int plane_row_stride(const Geo& g) {
+  return plane_row_stride_ce(g.ny, g.nz, plane_plan_y(g), plane_plan_z(g));
 }
 
 // Lane budget of one line in pass B: a 1024-thread workgroup shared by the
@@ -739,9 +745,13 @@ struct PlansCT {
 // DERIV: multiply by d/dlambda of the multiplier (generic kernel only).
 template <int NY, int NZ, bool DERIV = false>
 __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan pz0, TeamPlan pzi0,
-                                                 XDivs xd, int rs, Tables tg, float2* __restrict__ X,
+                                                 XDivs xd, int rs_host, Tables tg, float2* __restrict__ X,
                                                  float lambda, float theta, int order) {
   extern __shared__ float2 lds[];
+  using PCT = PlansCT<NY ? NY : 32, NZ ? NZ : 32>;
+  // compile-time sizes: the same row stride as the host's, as a constant
+  constexpr int kRs = NY ? plane_row_stride_ce(NY ? NY : 32, NZ ? NZ : 32, PCT::PY, PCT::PZ) : 0;
+  const int rs = NY ? kRs : rs_host;
   // run-time plans are indexed by stage: keep them in LDS
   __shared__ __align__(16) unsigned char plan_mem[NY == 0 ? 3 * sizeof(TeamPlan) : 16];
   TeamPlan* plans = reinterpret_cast<TeamPlan*>(plan_mem);
@@ -766,7 +776,6 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   // Compile-time sizes: the host launches at least ceil(nz / nlw_y) and
   // ceil(ny / nlw_z) wavefronts when both are <= 16, so every wavefront owns at
   // most one group of rows and one group of columns (no loop over groups).
-  using PCT = PlansCT<NY ? NY : 32, NZ ? NZ : 32>;
   constexpr int kNlwY = 64 / PCT::PY.L, kNlwZ = 64 / PCT::PZ.L;
   constexpr bool ONE_PASS = NY > 0 && (NZ + kNlwY - 1) / kNlwY <= 16 && (NY + kNlwZ - 1) / kNlwZ <= 16;
 
