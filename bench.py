@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
-KERNEL_SOURCES = ["kernels.hip", "kernels.h", "fft_lds.h"]
+KERNEL_SOURCES = ["kernels.hip", "kernels.h", "fft_lds.h", "pointwise.h"]
 # rocprofv3 kernel-name prefixes of the replayable kernels
 KERNEL_NAMES = {"pass_a_fwd_x": "nadmm::k_pass_a<", "pass_b_yz_solve": "nadmm::k_pass_b<",
                 "pass_ca_iter": "nadmm::k_pass_c<5,"}

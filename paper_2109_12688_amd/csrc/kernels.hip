@@ -289,7 +289,7 @@ __global__ void k_warp(Geo g, const T* __restrict__ img, const float* __restrict
   out = at_pair(out, g.V, blockIdx.y);
   const int x = i % g.nx, y = (i / g.nx) % g.ny, z = i / (g.nx * g.ny);
   const Tap t = make_tap(x, y, z, disp[i], disp[g.V + i], disp[2 * g.V + i], g);
-  out[i] = sample(img, t);
+  store_wt(out + i, sample(img, t));
 }
 
 template <typename T>
@@ -334,20 +334,20 @@ __global__ void k_grad_resid(Geo g, const float* __restrict__ iw, const T* __res
   j[1] = (iw[yp] - iw[ym]) * 0.5f;
   j[2] = (iw[zp] - iw[zm]) * 0.5f;
   if (grad) {
-    grad[i] = j[0];
-    grad[g.V + i] = j[1];
-    grad[2 * g.V + i] = j[2];
+    store_wt(grad + i, j[0]);
+    store_wt(grad + g.V + i, j[1]);
+    store_wt(grad + 2 * g.V + i, j[2]);
   }
   if (ref) {
     const float r = iw[i] - img_at(ref, i);
-    if (resid) resid[i] = r;
+    if (resid) store_wt(resid + i, r);
     if (s0) {
       const float a[3] = {0.f, 0.f, 0.f};
       float v[3];
       data_step(a, j, r, theta, eps, data_term, v);
-      s0[i] = v[0];
-      s0[g.V + i] = v[1];
-      s0[2 * g.V + i] = v[2];
+      store_wt(s0 + i, v[0]);
+      store_wt(s0 + g.V + i, v[1]);
+      store_wt(s0 + 2 * g.V + i, v[2]);
     }
   }
 }
@@ -402,9 +402,9 @@ __global__ void k_compose(Geo g, const float* __restrict__ u, const float* __res
   const int x = i % g.nx, y = (i / g.nx) % g.ny, z = i / (g.nx * g.ny);
   const float vx = v[i], vy = v[g.V + i], vz = v[2 * g.V + i];
   const Tap t = make_tap(x, y, z, vx, vy, vz, g);
-  out[i] = vx + sample(u, t);
-  out[g.V + i] = vy + sample(u + g.V, t);
-  out[2 * g.V + i] = vz + sample(u + 2 * g.V, t);
+  store_wt(out + i, vx + sample(u, t));
+  store_wt(out + g.V + i, vy + sample(u + g.V, t));
+  store_wt(out + 2 * g.V + i, vz + sample(u + 2 * g.V, t));
 }
 
 hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out,
@@ -575,7 +575,7 @@ __device__ __forceinline__ void store_half_spectrum(const Geo& g, const XDivs& x
       const float2 z0 = Z[0], zn = Z[lpad<XL_PADSH>(nh)];
       o = make_float4(z0.x * s1, 0.f, z0.y * s1, 0.f);
       float2* dn = X + ((size_t)(c * (nh + 1) + nh) * g.nz + z) * g.ny + y0 + 2 * yp;
-      *reinterpret_cast<float4*>(dn) = make_float4(zn.x * s1, 0.f, zn.y * s1, 0.f);
+      store_wt(reinterpret_cast<float4*>(dn), make_float4(zn.x * s1, 0.f, zn.y * s1, 0.f));
     } else {
       const float2 zk = Z[lpad<XL_PADSH>(k)], zm = Z[lpad<XL_PADSH>(nx - k)];
       // a = (Zk + conj(Zm)) / 2 ; b = -i (Zk - conj(Zm)) / 2
@@ -583,7 +583,7 @@ __device__ __forceinline__ void store_half_spectrum(const Geo& g, const XDivs& x
                       -sh * (zk.x - zm.x));
     }
     float2* dst = X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y0 + 2 * yp;
-    *reinterpret_cast<float4*>(dst) = o;
+    store_wt(reinterpret_cast<float4*>(dst), o);
   }
 }
 
@@ -905,7 +905,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
         const int zz = NY ? i / NY : (int)fdiv((uint32_t)i, xd.ny), yy = i - zz * ny;
         const float2* sp = buf + (l0 + zz) * rs + lpad<4>(yy);
         const float2 a = sp[0], b = sp[1];
-        out4[l0 * (ny / 2) + idx] = make_float4(a.x, a.y, b.x, b.y);
+        store_wt(out4 + l0 * (ny / 2) + idx, make_float4(a.x, a.y, b.x, b.y));
       }
     }
   }
@@ -956,7 +956,7 @@ __global__ void __launch_bounds__(256) k_split_rows(Geo g, FftPlan py, FastDiv d
     const int row = NY ? idx / (NY / 2) : (int)fdiv((uint32_t)idx, dq);
     const int e = 2 * (idx - row * half);
     const float2* d = buf + row * ls + lpad<4>(e);
-    base[idx] = make_float4(d[0].x, d[0].y, d[1].x, d[1].y);
+    store_wt(base + idx, make_float4(d[0].x, d[0].y, d[1].x, d[1].y));
   }
 }
 
@@ -1008,7 +1008,7 @@ __global__ void __launch_bounds__(256) k_split_cols(Geo g, FftPlan pz, FastDiv d
   for (int idx = threadIdx.x; idx < items; idx += nthr) {
     const int rr = idx >> hs, jj = idx - (rr << hs);
     const float2 a = buf[(2 * jj) * ls + lpad<4>(rr)], b = buf[(2 * jj + 1) * ls + lpad<4>(rr)];
-    *reinterpret_cast<float4*>(plane + (size_t)rr * ny + q0 + 2 * jj) = make_float4(a.x, a.y, b.x, b.y);
+    store_wt(reinterpret_cast<float4*>(plane + (size_t)rr * ny + q0 + 2 * jj), make_float4(a.x, a.y, b.x, b.y));
   }
 }
 
@@ -1138,7 +1138,7 @@ hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda,
 // pass C: half spectrum -> y = S t, then the mode's pointwise work
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
-__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+__device__ __forceinline__ void st4(float* p, float4 v) { store_wt(reinterpret_cast<float4*>(p), v); }
 __device__ __forceinline__ float f4get(const float4& v, int e) {
   return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
 }

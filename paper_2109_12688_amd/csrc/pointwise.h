@@ -9,6 +9,28 @@
 namespace nadmm {
 
 // ---------------------------------------------------------------------------
+// stores of results that a later kernel reads
+// ---------------------------------------------------------------------------
+// System scope (sc0 sc1): the L2 of the storing XCD writes them through, so
+// the release at the end of the kernel finds no dirty lines to write back
+// from the eight XCD caches before the next launch, whose workgroups read
+// them from every XCD.  The pointers are global device memory.
+//
+// A VALU write to the data registers of a vector-memory store of more than
+// 64 bits must come at least one wait state after the store.  The compiler
+// inserts that wait for the stores it emits, not for stores inside inline
+// asm, so the 128-bit form carries its own s_nop.
+__device__ __forceinline__ void store_wt(float* p, float v) {
+  asm volatile("global_store_dword %0, %1, off sc0 sc1" : : "v"(p), "v"(v) : "memory");
+}
+__device__ __forceinline__ void store_wt(float4* p, float4 v) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v w = {v.x, v.y, v.z, v.w};
+  asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1\n\ts_nop 1" : : "v"(p), "v"(w)
+               : "memory");
+}
+
+// ---------------------------------------------------------------------------
 // periodic trilinear sampling
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrap_index(int i, int n) {
