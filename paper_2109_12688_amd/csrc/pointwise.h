@@ -33,7 +33,10 @@ __device__ __forceinline__ void store_wt(float4* p, float4 v) {
 // ---------------------------------------------------------------------------
 // periodic trilinear sampling
 // ---------------------------------------------------------------------------
+// i mod n in [0, n) for every i; [-n, 2n) (displacements shorter than the
+// grid) without a division.
 __device__ __forceinline__ int wrap_index(int i, int n) {
+  if (i >= -n && i < 2 * n) return i < 0 ? i + n : (i >= n ? i - n : i);
   i %= n;
   return i < 0 ? i + n : i;
 }
@@ -52,8 +55,11 @@ __device__ __forceinline__ void cell(int x, float u, int n, int& i0, int& i1, fl
 
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
+// Element offsets of the eight corners (unsigned 32-bit: a volume holds at
+// most 2^30 voxels), so that loads address memory as a scalar base plus a
+// 32-bit vector offset.
 struct Tap {
-  int o000, o100, o010, o110, o001, o101, o011, o111;
+  uint32_t o000, o100, o010, o110, o001, o101, o011, o111;
   float tx, ty, tz;
 };
 
@@ -64,8 +70,9 @@ __device__ __forceinline__ Tap make_tap(int x, int y, int z, float ux, float uy,
   cell(x, ux, g.nx, x0, x1, t.tx);
   cell(y, uy, g.ny, y0, y1, t.ty);
   cell(z, uz, g.nz, z0, z1, t.tz);
-  const int r00 = (z0 * g.ny + y0) * g.nx, r01 = (z0 * g.ny + y1) * g.nx;
-  const int r10 = (z1 * g.ny + y0) * g.nx, r11 = (z1 * g.ny + y1) * g.nx;
+  const uint32_t nx = g.nx, ny = g.ny;
+  const uint32_t r00 = ((uint32_t)z0 * ny + y0) * nx, r01 = ((uint32_t)z0 * ny + y1) * nx;
+  const uint32_t r10 = ((uint32_t)z1 * ny + y0) * nx, r11 = ((uint32_t)z1 * ny + y1) * nx;
   t.o000 = r00 + x0; t.o100 = r00 + x1;
   t.o010 = r01 + x0; t.o110 = r01 + x1;
   t.o001 = r10 + x0; t.o101 = r10 + x1;
@@ -74,9 +81,12 @@ __device__ __forceinline__ Tap make_tap(int x, int y, int z, float ux, float uy,
 }
 
 // Image element as float32: bfloat16 is the upper half of a float32.
-__device__ __forceinline__ float img_at(const float* __restrict__ f, int i) { return f[i]; }
-__device__ __forceinline__ float img_at(const uint16_t* __restrict__ f, int i) {
-  return __uint_as_float((uint32_t)f[i] << 16);
+__device__ __forceinline__ float img_at(const float* __restrict__ f, uint32_t i) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(f) + (i << 2));
+}
+__device__ __forceinline__ float img_at(const uint16_t* __restrict__ f, uint32_t i) {
+  const uint16_t b = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(f) + (i << 1));
+  return __uint_as_float((uint32_t)b << 16);
 }
 
 template <typename T>
@@ -85,6 +95,37 @@ __device__ __forceinline__ float sample(const T* __restrict__ f, const Tap& t) {
   const float c10 = lerpf(img_at(f, t.o010), img_at(f, t.o110), t.tx);
   const float c01 = lerpf(img_at(f, t.o001), img_at(f, t.o101), t.tx);
   const float c11 = lerpf(img_at(f, t.o011), img_at(f, t.o111), t.tx);
+  return lerpf(lerpf(c00, c10, t.ty), lerpf(c01, c11, t.ty), t.tz);
+}
+
+// Two consecutive floats from a 4-byte aligned address (one 8-byte load).
+typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+__device__ __forceinline__ float2_a4 ld2_at(const float* __restrict__ f, uint32_t i) {
+  return *reinterpret_cast<const float2_a4*>(reinterpret_cast<const char*>(f) + (i << 2));
+}
+
+// float32 fields: unless a cell of the wavefront wraps at the x edge, the
+// two x taps of each corner pair are adjacent and one 8-byte load fetches
+// both (half the addresses of the gather; the same values and arithmetic as
+// above).  The test is wavefront-uniform.
+template <>
+__device__ __forceinline__ float sample(const float* __restrict__ f, const Tap& t) {
+  float a000, a100, a010, a110, a001, a101, a011, a111;
+  if (__all(t.o100 == t.o000 + 1)) {
+    const float2_a4 p00 = ld2_at(f, t.o000), p10 = ld2_at(f, t.o010);
+    const float2_a4 p01 = ld2_at(f, t.o001), p11 = ld2_at(f, t.o011);
+    a000 = p00.x; a100 = p00.y; a010 = p10.x; a110 = p10.y;
+    a001 = p01.x; a101 = p01.y; a011 = p11.x; a111 = p11.y;
+  } else {
+    a000 = img_at(f, t.o000); a100 = img_at(f, t.o100);
+    a010 = img_at(f, t.o010); a110 = img_at(f, t.o110);
+    a001 = img_at(f, t.o001); a101 = img_at(f, t.o101);
+    a011 = img_at(f, t.o011); a111 = img_at(f, t.o111);
+  }
+  const float c00 = lerpf(a000, a100, t.tx);
+  const float c10 = lerpf(a010, a110, t.tx);
+  const float c01 = lerpf(a001, a101, t.tx);
+  const float c11 = lerpf(a011, a111, t.tx);
   return lerpf(lerpf(c00, c10, t.ty), lerpf(c01, c11, t.ty), t.tz);
 }
 
