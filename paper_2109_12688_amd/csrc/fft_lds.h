@@ -212,10 +212,51 @@ struct DftComposite {
   }
 };
 
+// Prime-factor (Good-Thomas) DFT of length R1*R2 for coprime R1, R2: with
+// n = (R2 n1 + R1 n2) mod R and k the index with k = k1 mod R1, k = k2 mod R2,
+// exp(-+2 pi i n k / R) = exp(-+2 pi i n1 k1 / R1) exp(-+2 pi i n2 k2 / R2),
+// so R2 DFTs of length R1 and R1 DFTs of length R2 need no twiddles between
+// them (both index maps are compile-time register permutations).
+template <int R1, int R2>
+struct PfaMaps {
+  int in[R2][R1];   // input index of (n1, n2)
+  int out[R1][R2];  // output index of (k1, k2)
+};
+template <int R1, int R2>
+constexpr PfaMaps<R1, R2> make_pfa_maps() {
+  PfaMaps<R1, R2> m{};
+  for (int n2 = 0; n2 < R2; ++n2)
+    for (int n1 = 0; n1 < R1; ++n1) m.in[n2][n1] = (R2 * n1 + R1 * n2) % (R1 * R2);
+  for (int k = 0; k < R1 * R2; ++k) m.out[k % R1][k % R2] = k;
+  return m;
+}
+template <int R1, int R2, bool INV>
+struct DftPfa {
+  static constexpr PfaMaps<R1, R2> M = make_pfa_maps<R1, R2>();
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[M.in[n2][n1]];
+      Dft<R1, INV>::run(a[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 b[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) b[n2] = a[n2][k1];
+      Dft<R2, INV>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[M.out[k1][k2]] = b[k2];
+    }
+  }
+};
+
 template <bool INV>
-struct Dft<6, INV> : DftComposite<2, 3, INV> {};
+struct Dft<6, INV> : DftPfa<2, 3, INV> {};
 template <bool INV>
-struct Dft<12, INV> : DftComposite<4, 3, INV> {};
+struct Dft<12, INV> : DftPfa<4, 3, INV> {};
 template <bool INV>
 struct Dft<16, INV> : DftComposite<4, 4, INV> {};
 
