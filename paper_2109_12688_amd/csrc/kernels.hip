@@ -1150,15 +1150,15 @@ __device__ __forceinline__ void f4set(float4& v, int e, float s) {
 // differences with unit spacing, the same operations as k_grad_resid.
 __device__ __forceinline__ void run_gradient(const Geo& g, int nx, const float* __restrict__ iw,
                                              int x0, int y, int z, float4 J[3]) {
-  const int ny = g.ny, nz = g.nz;
-  const float* row = iw + (size_t)(z * ny + y) * nx;
-  const float4 c = ld4(row + x0);
-  const float xm = row[x0 == 0 ? nx - 1 : x0 - 1];
-  const float xp = row[x0 + 4 == nx ? 0 : x0 + 4];
-  const float4 ym = ld4(iw + (size_t)(z * ny + (y == 0 ? ny - 1 : y - 1)) * nx + x0);
-  const float4 yp = ld4(iw + (size_t)(z * ny + (y + 1 == ny ? 0 : y + 1)) * nx + x0);
-  const float4 zm = ld4(iw + (size_t)((z == 0 ? nz - 1 : z - 1) * ny + y) * nx + x0);
-  const float4 zp = ld4(iw + (size_t)((z + 1 == nz ? 0 : z + 1) * ny + y) * nx + x0);
+  const uint32_t ny = g.ny, nz = g.nz, n = nx;
+  const uint32_t row = ((uint32_t)z * ny + y) * n;
+  const float4 c = ld4_at(iw, row + x0);
+  const float xm = img_at(iw, row + (x0 == 0 ? nx - 1 : x0 - 1));
+  const float xp = img_at(iw, row + (x0 + 4 == nx ? 0 : x0 + 4));
+  const float4 ym = ld4_at(iw, ((uint32_t)z * ny + (y == 0 ? ny - 1 : y - 1)) * n + x0);
+  const float4 yp = ld4_at(iw, ((uint32_t)z * ny + (y + 1 == (int)ny ? 0 : y + 1)) * n + x0);
+  const float4 zm = ld4_at(iw, ((z == 0 ? nz - 1 : z - 1) * ny + y) * n + x0);
+  const float4 zp = ld4_at(iw, ((z + 1 == (int)nz ? 0 : z + 1) * ny + y) * n + x0);
   J[0] = make_float4((c.y - xm) * 0.5f, (c.z - c.x) * 0.5f, (c.w - c.y) * 0.5f, (xp - c.z) * 0.5f);
   J[1] = make_float4((yp.x - ym.x) * 0.5f, (yp.y - ym.y) * 0.5f, (yp.z - ym.z) * 0.5f,
                      (yp.w - ym.w) * 0.5f);
@@ -1288,12 +1288,12 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
       float4 s1v[3], s2v[3], jv[3], yr[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        s1v[c] = ld4(a.s1 + c * g.V + go);
-        s2v[c] = a.s2 ? ld4(a.s2 + c * g.V + go) : s1v[c];
-        if constexpr (MODE == kIterFwd) jv[c] = ld4(a.J + c * g.V + go);
+        s1v[c] = ld4_at(a.s1 + c * g.V, go);
+        s2v[c] = a.s2 ? ld4_at(a.s2 + c * g.V, go) : s1v[c];
+        if constexpr (MODE == kIterFwd) jv[c] = ld4_at(a.J + c * g.V, go);
       }
       if constexpr (MODE == kIterFwdIw) run_gradient(g, nx, a.iw, x0, y0 + yy, z, jv);
-      const float4 rv = ld4(a.r + go);
+      const float4 rv = ld4_at(a.r, go);
       float* slot[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1322,8 +1322,8 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
       const float gn = a.gamma_next;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        st4(a.out + c * g.V + go, so[c]);
-        if (a.v_out) st4(a.v_out + c * g.V + go, vo[c]);
+        store_wt_at(a.out + c * g.V, go, so[c]);
+        if (a.v_out) store_wt_at(a.v_out + c * g.V, go, vo[c]);
         // next solve's input t' = s^k + gamma_next (s^k - s^{k-1}), written
         // over the slots this thread read y from
         const float4 n = so[c], o = s1v[c];

@@ -29,6 +29,17 @@ __device__ __forceinline__ void store_wt(float4* p, float4 v) {
   asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1\n\ts_nop 1" : : "v"(p), "v"(w)
                : "memory");
 }
+// The same at element i of a wavefront-uniform base (a scalar base plus a
+// 32-bit byte offset: one array of at most 2^30 floats).
+__device__ __forceinline__ void store_wt_at(float* base, uint32_t i, float4 v) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v w = {v.x, v.y, v.z, v.w};
+  asm volatile("global_store_dwordx4 %0, %1, %2 sc0 sc1\n\ts_nop 1" : : "v"(i << 2), "v"(w),
+               "s"(base) : "memory");
+}
+__device__ __forceinline__ float4 ld4_at(const float* __restrict__ base, uint32_t i) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(base) + (i << 2));
+}
 
 // ---------------------------------------------------------------------------
 // periodic trilinear sampling
@@ -140,7 +151,7 @@ __device__ __forceinline__ void data_step(const float a[3], const float j[3], fl
   const float jj = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
   float f;
   if (data_term == 2) {
-    f = (ja + r) / (theta + jj);
+    f = (ja + r) * __builtin_amdgcn_rcpf(theta + jj);
   } else {
     const float z = theta * (ja + r) / (jj + eps);
     f = (z / fmaxf(fabsf(z), 1.0f)) / theta;
