@@ -501,14 +501,14 @@ constexpr bool team_search(int n, int m, int L, int depth, int* out) {
   return false;
 }
 
-constexpr TeamPlan make_team_plan_ce(int n, int max_lanes, int min_lanes = 1) {
+constexpr TeamPlan make_team_plan_ce(int n, int max_lanes) {
   TeamPlan best{};
   best.n = n;
   best.nstages = -1;
   const int Ls[5] = {16, 8, 4, 2, 1};
   for (int li = 0; li < 5; ++li) {
     const int L = Ls[li];
-    if (L > max_lanes || L < min_lanes || n % L || n / L > kTeamEpt) continue;
+    if (L > max_lanes || n % L || n / L > kTeamEpt) continue;
     int rad[4] = {0, 0, 0, 0};
     for (int depth = 1; depth <= 4; ++depth) {
       if (team_search(n, n, L, depth, rad)) {

@@ -35,41 +35,30 @@
 #include "pointwise.h"
 
 // Layout of the x-line buffers of passes A and C: butterflies of one line on
-// consecutive threads (XL_LINE_FAST 0) and one padding slot every
-// 2^XL_PADSH complex elements, plus XL_EXTRA slots at the end of each line.
-#ifndef XL_LINE_FAST
-#define XL_LINE_FAST 0
-#endif
-#ifndef XL_PADSH
-#define XL_PADSH 4
-#endif
-static_assert(XL_PADSH == 0 || XL_PADSH >= 2, "float4 runs must not straddle a padding slot");
-#ifndef XL_EXTRA
-#define XL_EXTRA 0
-#endif
+// consecutive threads and one padding slot every 2^kXlPadsh complex elements.
+constexpr int kXlPadsh = 4;
+static_assert(kXlPadsh >= 2, "float4 runs must not straddle a padding slot");
 // Rows of one z-slice per workgroup of the x-line passes (largest even
-// divisor of ny up to this).
-#ifndef XL_MAX_ROWS
-#define XL_MAX_ROWS 8
-#endif
+// divisor of ny up to this; the autotuner may pick fewer).
+constexpr int kXlMaxRows = 8;
 
 namespace nadmm {
 
-static inline int xl_pad_host(int e) { return XL_PADSH > 0 ? e + (e >> XL_PADSH) : e; }
+static inline int xl_pad_host(int e) { return kXlPadsh > 0 ? e + (e >> kXlPadsh) : e; }
 // complex elements between consecutive x lines in LDS
-static inline int xline_stride(int nx) { return xl_pad_host(nx) + XL_EXTRA; }
+static inline int xline_stride(int nx) { return xl_pad_host(nx); }
 
 // ---------------------------------------------------------------------------
 // host-side geometry helpers
 // ---------------------------------------------------------------------------
 // Rows per x-line workgroup: the tuned value for these sizes when one was
 // set (xline_rows_set, from the autotuner), else the largest even divisor of
-// ny up to XL_MAX_ROWS.
+// ny up to kXlMaxRows.
 static std::mutex g_rows_mu;
 static std::map<std::tuple<int, int, int>, int> g_rows;
 
 int xline_rows_default(int ny) {
-  for (int yb = XL_MAX_ROWS; yb >= 2; yb -= 2)
+  for (int yb = kXlMaxRows; yb >= 2; yb -= 2)
     if (ny % yb == 0) return yb;
   return 2;
 }
@@ -104,12 +93,10 @@ int xline_threads(const Geo& g) {
   return t;
 }
 
-#ifndef PLANE_EPT_TARGET
-#define PLANE_EPT_TARGET 8
-#endif
+constexpr int kPlaneEptTarget = 8;  // points per thread the plane pass is sized for
 int plane_threads(const Geo& g) {
   const int elems = g.ny * g.nz;
-  int t = round_up((elems + PLANE_EPT_TARGET - 1) / PLANE_EPT_TARGET, 64);
+  int t = round_up((elems + kPlaneEptTarget - 1) / kPlaneEptTarget, 64);
   if (t > 1024) t = 1024;
   if (t < 64) t = 64;
   return t;
@@ -191,15 +178,7 @@ static int lane_budget(int nlines) {
   return b < 1 ? 1 : b;
 }
 TeamPlan plane_plan_y(const Geo& g) { return make_team_plan(g.ny, lane_budget(g.nz)); }
-// Smallest team for the z lines (a tuning knob: larger teams put more
-// wavefronts on the columns at the cost of more stages).
-#ifndef PLANE_Z_MIN_LANES
-#define PLANE_Z_MIN_LANES 1
-#endif
-TeamPlan plane_plan_z(const Geo& g) {
-  TeamPlan p = make_team_plan_ce(g.nz, lane_budget(g.ny), PLANE_Z_MIN_LANES);
-  return p.nstages > 0 ? p : make_team_plan(g.nz, lane_budget(g.ny));
-}
+TeamPlan plane_plan_z(const Geo& g) { return make_team_plan(g.nz, lane_budget(g.ny)); }
 
 static int plane_team_threads(const Geo& g) {
   const TeamPlan py = plane_plan_y(g), pz = plane_plan_z(g);
@@ -527,14 +506,11 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st) {
 // round-robin over the 8 XCDs, each with its own L2; when the grid allows,
 // each XCD gets one contiguous range of tiles instead, so that neighbouring
 // tiles (which share 128-byte lines of the half spectrum, and z-planes for
-// the gathers) meet in the same L2.  (XCD_REMAP 0 keeps the hardware order.)
-#ifndef XCD_REMAP
-#define XCD_REMAP 1
-#endif
+// the gathers) meet in the same L2.
 __device__ __forceinline__ void xline_tile(int& by, int& z) {
   const int nby = gridDim.x, n = gridDim.x * gridDim.y;
   int l = blockIdx.x + nby * blockIdx.y;
-  if (XCD_REMAP && (n & 7) == 0) l = (l & 7) * (n >> 3) + (l >> 3);
+  if ((n & 7) == 0) l = (l & 7) * (n >> 3) + (l >> 3);
   z = l / nby;
   by = l - z * nby;
 }
@@ -544,10 +520,10 @@ __device__ __forceinline__ void xline_tile(int& by, int& z) {
 template <int NX, bool INV>
 __device__ __forceinline__ void x_transform(float2* buf, const float2* tw, const FftPlan& px,
                                             const XDivs& xd, int ls) {
-  if constexpr (NX > 0 && XL_LINE_FAST == 0)
-    fft_lines_ct<NX, kEpt, INV, XL_PADSH>(buf, tw, (int)xd.lines.d, ls);
+  if constexpr (NX > 0)
+    fft_lines_ct<NX, kEpt, INV, kXlPadsh>(buf, tw, (int)xd.lines.d, ls);
   else
-    fft_lines<kEpt, INV, XL_LINE_FAST, XL_PADSH>(buf, tw, px, xd.lines, 1, ls);
+    fft_lines<kEpt, INV, false, kXlPadsh>(buf, tw, px, xd.lines, 1, ls);
 }
 
 // Split the transformed line pairs of one block into the two rows' half
@@ -572,12 +548,12 @@ __device__ __forceinline__ void store_half_spectrum(const Geo& g, const XDivs& x
     const float2* Z = buf + (c * yb2 + yp) * ls;
     float4 o;
     if (k == 0) {
-      const float2 z0 = Z[0], zn = Z[lpad<XL_PADSH>(nh)];
+      const float2 z0 = Z[0], zn = Z[lpad<kXlPadsh>(nh)];
       o = make_float4(z0.x * s1, 0.f, z0.y * s1, 0.f);
       float2* dn = X + ((size_t)(c * (nh + 1) + nh) * g.nz + z) * g.ny + y0 + 2 * yp;
       store_wt(reinterpret_cast<float4*>(dn), make_float4(zn.x * s1, 0.f, zn.y * s1, 0.f));
     } else {
-      const float2 zk = Z[lpad<XL_PADSH>(k)], zm = Z[lpad<XL_PADSH>(nx - k)];
+      const float2 zk = Z[lpad<kXlPadsh>(k)], zm = Z[lpad<kXlPadsh>(nx - k)];
       // a = (Zk + conj(Zm)) / 2 ; b = -i (Zk - conj(Zm)) / 2
       o = make_float4(sh * (zk.x + zm.x), sh * (zk.y - zm.y), sh * (zk.y + zm.y),
                       -sh * (zk.x - zm.x));
@@ -640,7 +616,7 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
                         fmaf(gamma, t.z - u.z, t.z), fmaf(gamma, t.w - u.w, t.w));
       }
       const int line = c * yb2 + (yy >> 1);
-      float* d = bf + 2 * (line * ls + lpad<XL_PADSH>(4 * x4)) + (yy & 1);
+      float* d = bf + 2 * (line * ls + lpad<kXlPadsh>(4 * x4)) + (yy & 1);
       d[0] = t.x;
       d[2] = t.y;
       d[4] = t.z;
@@ -711,8 +687,7 @@ constexpr int lane_budget_ce(int nlines) { return 1024 / nlines < 1 ? 1 : 1024 /
 template <int NY, int NZ>
 struct PlansCT {
   static constexpr TeamPlan PY = make_team_plan_ce(NY, lane_budget_ce(NZ));
-  static constexpr TeamPlan PZ0 = make_team_plan_ce(NZ, lane_budget_ce(NY), PLANE_Z_MIN_LANES);
-  static constexpr TeamPlan PZ = PZ0.nstages > 0 ? PZ0 : make_team_plan_ce(NZ, lane_budget_ce(NY));
+  static constexpr TeamPlan PZ = make_team_plan_ce(NZ, lane_budget_ce(NY));
   static constexpr TeamPlan PZI = reverse_team_plan_ce(PZ);
   static_assert(PY.nstages > 0 && PZ.nstages > 0, "no wave-team plan for this size");
   __device__ int ly() const { return PY.L; }
@@ -1239,10 +1214,10 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
         // real DC and Nyquist bins of the two rows (imaginary parts are zero)
         const float4 qn = inn[it];
         Z[0] = make_float2(q.x, q.z);
-        Z[lpad<XL_PADSH>(nh)] = make_float2(qn.x, qn.z);
+        Z[lpad<kXlPadsh>(nh)] = make_float2(qn.x, qn.z);
       } else {
-        Z[lpad<XL_PADSH>(k)] = make_float2(q.x - q.w, q.y + q.z);
-        Z[lpad<XL_PADSH>(nx - k)] = make_float2(q.x + q.w, q.z - q.y);
+        Z[lpad<kXlPadsh>(k)] = make_float2(q.x - q.w, q.y + q.z);
+        Z[lpad<kXlPadsh>(nx - k)] = make_float2(q.x + q.w, q.z - q.y);
       }
     }
   }
@@ -1254,7 +1229,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
   auto run_slot = [&](int it, int c) {
     const int idx = threadIdx.x + it * nthr;
     const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
-    return bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<XL_PADSH>(4 * x4)) + (yy & 1);
+    return bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<kXlPadsh>(4 * x4)) + (yy & 1);
   };
   float4 yv[MI][3];
   if (MODE != kIterFwd && MODE != kIterFwdIw) {
