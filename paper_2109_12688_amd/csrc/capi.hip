@@ -228,12 +228,19 @@ hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const
 // s^{iters-1} and X the pass-B output for S s^{iters-1}, ready for the
 // warping's final pass C.
 // J given, or (J null) recomputed in the fused pass from the warped source iw.
+// x_done: the x transform of s^0 is already in X (pass A fused with the
+// data term), so the first solve starts at pass B.
 nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
                              const nadmm_params* p, const float* J, const float* iw,
                              const float* r, float*& cur, float*& prev, float2* X, float* v_last,
-                             hipStream_t st, int batch = 1) {
+                             hipStream_t st, int batch = 1, bool x_done = false) {
   const std::vector<double> gam = nesterov_gammas(p->iters);
-  HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st, batch));  // gamma_0 = 0: t = s^0
+  if (x_done)
+    HIP_TRY(timed(KK_PASS_B, st, [&] {
+      return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch);
+    }));
+  else
+    HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st, batch));  // gamma_0 = 0: t = s^0
   for (int k = 1; k < p->iters; ++k) {
     PassCArgs a{};
     a.X = X;
@@ -315,11 +322,12 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
     const bool last = (c == p->outer - 1);
     // linearised data term at the current warp, and s^0 (Eq. (6) from zero)
     // r and s^0 only: the iterations recompute J = grad I1^w from iw
-    HIP_TRY(timed(KK_GRAD, st, [&] { return launch_grad_resid(g, iw, fixed, nullptr, r, S1, (float)p->theta, (float)p->eps,
-                              p->data_term, st, batch); }));
+    // (fused with the x transform of s^0)
+    HIP_TRY(timed(KK_PASS_A, st, [&] { return launch_pass_a0(g, pl.x, tb, iw, fixed, r, S1, (float)p->theta,
+                              (float)p->eps, p->data_term, X, st, batch); }));
     float* cur = S1;
     float* prev = S2;
-    CHECK(admm_iterations(g, pl, tb, p, nullptr, iw, r, cur, prev, X, nullptr, st, batch));
+    CHECK(admm_iterations(g, pl, tb, p, nullptr, iw, r, cur, prev, X, nullptr, st, batch, true));
     // final w = S s^{K-1}, composed onto the displacement
     PassCArgs a{};
     a.X = X;

@@ -126,6 +126,14 @@ hipError_t launch_admm_init(const Geo& g, const float* J, const float* r, float*
                             float theta, float eps, int data_term, hipStream_t st);
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
                          const float* s2, float gamma, float2* X, hipStream_t st, int batch = 1);
+// Pass A from the data term at the start of a warping: r = iw - ref and
+// s^0 (the data step from zero, J = grad iw) stored, s^0 transformed along x.
+hipError_t launch_pass_a0(const Geo& g, const FftPlan& px, const Tables& t, const float* iw,
+                          const float* ref, float* r, float* s0, float theta, float eps,
+                          int data_term, float2* X, hipStream_t st, int batch = 1);
+hipError_t launch_pass_a0(const Geo& g, const FftPlan& px, const Tables& t, const float* iw,
+                          const uint16_t* ref, float* r, float* s0, float theta, float eps,
+                          int data_term, float2* X, hipStream_t st, int batch = 1);
 // deriv: multiply by d/dlambda of the w-step multiplier instead of the multiplier.
 hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
                          int order, hipStream_t st, int batch = 1, bool deriv = false);

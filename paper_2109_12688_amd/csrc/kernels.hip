@@ -1141,6 +1141,103 @@ __device__ __forceinline__ void run_gradient(const Geo& g, int nx, const float* 
                      (zp.w - zm.w) * 0.5f);
 }
 
+// Pass A at the start of a warping, fused with the linearised data term:
+// per run of 4 voxels J = grad I1^w (the differences of k_grad_resid),
+// r = I1^w - I0 and s^0 = the data step from zero, stored (the first
+// iteration reads both) and transformed along x as pass A transforms s^0.
+template <int NX, typename T>
+__global__ void __launch_bounds__(768) k_pass_a0(Geo g, FftPlan px, XDivs xd, int ls,
+                                                 const float2* __restrict__ twx,
+                                                 const float* __restrict__ iw,
+                                                 const T* __restrict__ ref, float* __restrict__ r_out,
+                                                 float* __restrict__ s0, float theta, float eps,
+                                                 int data_term, float2* __restrict__ X) {
+  extern __shared__ float2 lds[];
+  const int nx = NX ? NX : g.nx, q4 = nx / 4;
+  iw = at_pair(iw, (size_t)g.V, blockIdx.z);
+  ref = at_pair(ref, (size_t)g.V, blockIdx.z);
+  r_out = at_pair(r_out, (size_t)g.V, blockIdx.z);
+  s0 = at_pair(s0, 3 * (size_t)g.V, blockIdx.z);
+  X = at_pair(X, spectrum_elems(g), blockIdx.z);
+  const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
+  float2* tw = lds;
+  float2* buf = lds + nx;
+  int by, z;
+  xline_tile(by, z);
+  const int y0 = by * yb;
+  const int nthr = blockDim.x;
+  for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
+  float* bf = reinterpret_cast<float*>(buf);
+  const int nitems = yb * q4;
+  for (int idx = threadIdx.x; idx < nitems; idx += nthr) {
+    const int yy = (int)fdiv((uint32_t)idx, xd.q4);
+    const int x0 = 4 * (idx - yy * q4);
+    const uint32_t go = ((uint32_t)z * g.ny + y0 + yy) * nx + x0;
+    float4 J[3];
+    run_gradient(g, nx, iw, x0, y0 + yy, z, J);
+    const float4 c = ld4_at(iw, go);
+    const float4 rv = make_float4(c.x - img_at(ref, go), c.y - img_at(ref, go + 1),
+                                  c.z - img_at(ref, go + 2), c.w - img_at(ref, go + 3));
+    store_wt_at(r_out, go, rv);
+    float4 sv[3];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float a[3] = {0.f, 0.f, 0.f};
+      const float j[3] = {f4get(J[0], e), f4get(J[1], e), f4get(J[2], e)};
+      float v[3];
+      data_step(a, j, f4get(rv, e), theta, eps, data_term, v);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) f4set(sv[cc], e, v[cc]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      store_wt_at(s0 + cc * g.V, go, sv[cc]);
+      float* d = bf + 2 * ((cc * yb2 + (yy >> 1)) * ls + lpad<kXlPadsh>(x0)) + (yy & 1);
+      d[0] = sv[cc].x;
+      d[2] = sv[cc].y;
+      d[4] = sv[cc].z;
+      d[6] = sv[cc].w;
+    }
+  }
+  __syncthreads();
+  x_transform<NX, false>(buf, tw, px, xd, ls);
+  store_half_spectrum<NX>(g, xd, ls, buf, X, y0, z);
+}
+
+template <typename T>
+static hipError_t pass_a0_any(const Geo& g, const FftPlan& px, const Tables& t, const float* iw,
+                              const T* ref, float* r, float* s0, float theta, float eps,
+                              int data_term, float2* X, hipStream_t st, int batch) {
+  const int yb = xline_rows(g);
+  const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads(g));
+  const size_t lds = pass_a_lds(g);
+  const XDivs xd = make_xdivs(g);
+  const int ls = xline_stride(g.nx);
+#define NADMM_PASS_A0(N)                                                                     \
+  hipLaunchKernelGGL((k_pass_a0<N, T>), grid, block, lds, st, g, px, xd, ls, t.twx, iw, ref, r, \
+                     s0, theta, eps, data_term, X)
+  switch (g.nx) {
+    case 32: NADMM_PASS_A0(32); break;
+    case 64: NADMM_PASS_A0(64); break;
+    case 96: NADMM_PASS_A0(96); break;
+    case 128: NADMM_PASS_A0(128); break;
+    case 192: NADMM_PASS_A0(192); break;
+    default: NADMM_PASS_A0(0); break;
+  }
+#undef NADMM_PASS_A0
+  return hipGetLastError();
+}
+hipError_t launch_pass_a0(const Geo& g, const FftPlan& px, const Tables& t, const float* iw,
+                          const float* ref, float* r, float* s0, float theta, float eps,
+                          int data_term, float2* X, hipStream_t st, int batch) {
+  return pass_a0_any(g, px, t, iw, ref, r, s0, theta, eps, data_term, X, st, batch);
+}
+hipError_t launch_pass_a0(const Geo& g, const FftPlan& px, const Tables& t, const float* iw,
+                          const uint16_t* ref, float* r, float* s0, float theta, float eps,
+                          int data_term, float2* X, hipStream_t st, int batch) {
+  return pass_a0_any(g, px, t, iw, ref, r, s0, theta, eps, data_term, X, st, batch);
+}
+
 template <int MODE, int NX>
 __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx, PassCArgs a) {
