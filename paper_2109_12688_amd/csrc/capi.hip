@@ -303,31 +303,40 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
   // Displacement buffers alternate between U and disp so that the last
   // warping writes disp.
   auto dst_of = [&](int c) { return ((p->outer - 1 - c) % 2 == 0) ? disp : U; };
-  const float* u_src;
-  if (init_disp) {
-    u_src = init_disp;
-  } else {
-    float* z = (p->outer > 0 && dst_of(0) == disp) ? U : disp;
-    HIP_TRY(timed(KK_FILL, st, [&] { return launch_fill(z, 0.0f, 3 * V * batch, st); }));
-    u_src = z;
-  }
+  // u_src null: no displacement yet (u = 0).  Then the first warped image is
+  // the moving image itself (sampling at the grid points is exact) and the
+  // first composition has nothing to gather.
+  const float* u_src = init_disp;
   if (p->outer == 0) {
-    if (u_src != disp) HIP_TRY(hipMemcpyAsync(disp, u_src, 3 * V * batch * sizeof(float),
-                                              hipMemcpyDeviceToDevice, st));
+    if (!u_src)
+      HIP_TRY(timed(KK_FILL, st, [&] { return launch_fill(disp, 0.0f, 3 * V * batch, st); }));
+    else if (u_src != disp)
+      HIP_TRY(hipMemcpyAsync(disp, u_src, 3 * V * batch * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (warped) HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, disp, warped, st, batch); }));
     return NADMM_OK;
   }
-  HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, u_src, iw, st, batch); }));
+  const float* iw_first = iw;  // I1^w of the first warping
+  if (u_src) {
+    HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, u_src, iw, st, batch); }));
+  } else if constexpr (kBf16) {
+    // widen the bfloat16 image: a warp by the zero field
+    float* z = dst_of(0) == disp ? U : disp;
+    HIP_TRY(timed(KK_FILL, st, [&] { return launch_fill(z, 0.0f, 3 * V * batch, st); }));
+    HIP_TRY(timed(KK_WARP, st, [&] { return launch_warp(g, moving, z, iw, st, batch); }));
+  } else {
+    iw_first = reinterpret_cast<const float*>(moving);
+  }
   for (int c = 0; c < p->outer; ++c) {
     const bool last = (c == p->outer - 1);
     // linearised data term at the current warp, and s^0 (Eq. (6) from zero)
     // r and s^0 only: the iterations recompute J = grad I1^w from iw
     // (fused with the x transform of s^0)
-    HIP_TRY(timed(KK_PASS_A, st, [&] { return launch_pass_a0(g, pl.x, tb, iw, fixed, r, S1, (float)p->theta,
+    const float* iw_c = c == 0 ? iw_first : iw;
+    HIP_TRY(timed(KK_PASS_A, st, [&] { return launch_pass_a0(g, pl.x, tb, iw_c, fixed, r, S1, (float)p->theta,
                               (float)p->eps, p->data_term, X, st, batch); }));
     float* cur = S1;
     float* prev = S2;
-    CHECK(admm_iterations(g, pl, tb, p, nullptr, iw, r, cur, prev, X, nullptr, st, batch, true));
+    CHECK(admm_iterations(g, pl, tb, p, nullptr, iw_c, r, cur, prev, X, nullptr, st, batch, true));
     // final w = S s^{K-1}, composed onto the displacement
     PassCArgs a{};
     a.X = X;

@@ -97,7 +97,7 @@ struct PassCArgs {
   float* out;        // kOutY: y; kIterFwd: s^k (may alias s2); kFinalWB: w; kCompose: new u
   float* v_out;      // kIterFwd: optional v^k
   float* b_out;      // kFinalWB: optional b
-  const float* u_old;  // kCompose: displacement before this warping
+  const float* u_old;  // kCompose: displacement before this warping (null: zero)
   const float* img;    // kCompose: moving image
   const uint16_t* img_bf16;  // kComposeBf16: moving image (bfloat16 bit patterns)
   float* iw_out;       // kCompose: optional moving(x + u_new(x))

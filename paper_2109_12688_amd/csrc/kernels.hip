@@ -1434,10 +1434,13 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const float w0 = f4get(yv[it][0], e), w1 = f4get(yv[it][1], e), w2 = f4get(yv[it][2], e);
-          const Tap t = make_tap(4 * x4 + e, y0 + yy, z, w0, w1, w2, g);
-          const float u0 = w0 + sample(a.u_old, t);
-          const float u1 = w1 + sample(a.u_old + g.V, t);
-          const float u2 = w2 + sample(a.u_old + 2 * g.V, t);
+          float u0 = w0, u1 = w1, u2 = w2;
+          if (a.u_old) {  // null: the previous displacement is zero
+            const Tap t = make_tap(4 * x4 + e, y0 + yy, z, w0, w1, w2, g);
+            u0 += sample(a.u_old, t);
+            u1 += sample(a.u_old + g.V, t);
+            u2 += sample(a.u_old + 2 * g.V, t);
+          }
           f4set(un[0], e, u0);
           f4set(un[1], e, u1);
           f4set(un[2], e, u2);
