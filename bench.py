@@ -41,11 +41,14 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 # Algorithmic bytes per voxel of each kernel kind (inputs read once, outputs
 # written once; float32 fields, packed half spectrum = 4 B per component).
 BYTES_PER_VOXEL = {
-    "pass_a_fwd_x": 24.0,        # s^0 12, write the half spectrum 12 (once per warping)
+    # the registration's first pass of a warping (k_pass_a0, timed as pass_a_fwd_x):
+    # I^w 4 + I0 4, write r 4 + s^0 12 + half spectrum 12; k_pass_a alone
+    # (nadmm_admm, the replay) reads s^0 12 and writes the spectrum 12
+    "pass_a_fwd_x": 36.0,
     "pass_b_yz_solve": 24.0,     # read + write the 3-component half spectrum
     "pass_ca_iter": 68.0,        # spectrum 12 + s^k, s^{k-1} 24 + I1^w 4 + r 4, write s 12 + spectrum 12
     "pass_c_compose": 44.0,      # spectrum 12 + u gather 12 + image gather 4, write u 12 + I^w 4
-    "grad_resid": 24.0,          # I^w 4 + I0 4, write r 4 + s^0 12 (J is recomputed where used)
+    "grad_resid": 24.0,          # I^w 4 + I0 4, write r 4 + s^0 12 (nadmm_warp and the gradient path)
     "warp": 20.0,                # u 12 + image 4, write 4
     "fill": 12.0,
 }
