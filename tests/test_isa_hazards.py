@@ -72,16 +72,26 @@ def test_checker_finds_a_planted_hazard():
                               "v_lshl_add_u64 v[30:31], v[26:27], 2, s[22:23]")]
 
 
-def test_library_code_object_has_no_store_data_hazard(tmp_path):
+def test_library_code_objects_have_no_store_data_hazard(tmp_path):
+    """Every translation unit's gfx950 code object: the .hip_fatbin section
+    holds one offload bundle per source file with device code."""
     tools = [os.path.join(LLVM, t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-objdump")]
     if not os.path.exists(LIB) or not all(os.path.exists(t) for t in tools):
         pytest.skip("library not built or ROCm LLVM tools missing")
-    fat, dev = tmp_path / "fat.bin", tmp_path / "dev.o"
+    fat = tmp_path / "fat.bin"
     subprocess.run([tools[0], f"--dump-section=.hip_fatbin={fat}", LIB], check=True)
-    subprocess.run([tools[1], "--type=o", "--unbundle", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
-                    f"--input={fat}", f"--output={dev}"], check=True)
-    text = subprocess.run([tools[2], "-d", "--mcpu=gfx950", str(dev)], check=True, capture_output=True,
-                          text=True).stdout
-    n_wide = sum(1 for i in _instructions(text) if WIDE_STORE.match(i))
+    data = fat.read_bytes()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    starts = [m.start() for m in re.finditer(re.escape(magic), data)]
+    assert len(starts) >= 2  # kernels.hip and adjoint.hip
+    n_wide = 0
+    for n, (a, b) in enumerate(zip(starts, starts[1:] + [len(data)])):
+        part, dev = tmp_path / f"part{n}.bin", tmp_path / f"dev{n}.o"
+        part.write_bytes(data[a:b])
+        subprocess.run([tools[1], "--type=o", "--unbundle", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                        f"--input={part}", f"--output={dev}"], check=True)
+        text = subprocess.run([tools[2], "-d", "--mcpu=gfx950", str(dev)], check=True, capture_output=True,
+                              text=True).stdout
+        n_wide += sum(1 for i in _instructions(text) if WIDE_STORE.match(i))
+        assert hazards(text) == [], f"code object {n}"
     assert n_wide > 0
-    assert hazards(text) == []
