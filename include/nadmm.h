@@ -244,6 +244,15 @@ nadmm_status nadmm_jacobian(nadmm_dims d, const float* disp, float* det, double*
                             int64_t* n_nonpos, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* Output check (not an operation of the paper): the number of NaN or
+ * infinite values among `count` volumes stored back to back at `field`
+ * (count = 3 for a displacement or velocity field, 1 for an image), written
+ * to *nonfinite (device int64).  Lets a caller test a registration's outputs
+ * on the device, in stream order, without a host synchronisation inside the
+ * library.  1 <= count <= 64; no workspace. */
+nadmm_status nadmm_count_nonfinite(nadmm_dims d, const float* field, int32_t count,
+                                   int64_t* nonfinite, void* stream);
+
 /* Kernel timing instrumentation, for benchmarks.  While enabled (enable != 0),
  * every kernel the library launches is bracketed by two HIP events recorded
  * on its stream.  Host-side bookkeeping only; no device memory is used.

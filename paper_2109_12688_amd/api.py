@@ -299,6 +299,19 @@ def jacobian(disp: torch.Tensor, want_det: bool = False, ws: torch.Tensor | None
     return stats, nneg, det
 
 
+def count_nonfinite(field: torch.Tensor) -> torch.Tensor:
+    """Device int64 [1]: number of NaN or infinite entries of a scalar volume
+    (nz, ny, nx) or of stacked volumes (C, nz, ny, nx)."""
+    _check(field, "field")
+    if field.dim() not in (3, 4):
+        raise ValueError("field must be (nz, ny, nx) or (C, nz, ny, nx)")
+    count = 1 if field.dim() == 3 else field.shape[0]
+    out = torch.empty(1, dtype=torch.int64, device=field.device)
+    _lib.call("nadmm_count_nonfinite", dims_of(field.shape), _ptr(field), ctypes.c_int32(count),
+              _ptr(out), _stream())
+    return out
+
+
 REPLAY_KINDS = {"pass_a_fwd_x": 0, "pass_b_yz_solve": 1, "pass_ca_iter": 2}
 
 

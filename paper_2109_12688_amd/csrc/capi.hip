@@ -888,6 +888,17 @@ nadmm_status nadmm_jacobian(nadmm_dims d, const float* disp, float* det, double*
   return NADMM_OK;
 }
 
+nadmm_status nadmm_count_nonfinite(nadmm_dims d, const float* field, int32_t count,
+                                   int64_t* nonfinite, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_ptr(field, "field", false));
+  CHECK(check_ptr(nonfinite, "nonfinite", false));
+  if (count < 1 || count > 64) return fail(NADMM_ERR_INVALID_ARG, "count must be in [1, 64]");
+  const size_t n = (size_t)count * d.nx * d.ny * d.nz;
+  HIP_TRY(launch_count_nonfinite(field, n, nonfinite, static_cast<hipStream_t>(stream)));
+  return NADMM_OK;
+}
+
 nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t kind, int32_t reps,
                                   void* workspace, size_t workspace_bytes, void* stream,
                                   double* avg_ms) {

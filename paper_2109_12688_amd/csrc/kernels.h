@@ -105,6 +105,8 @@ struct PassCArgs {
 };
 
 hipError_t launch_fill(float* p, float value, size_t n, hipStream_t st);
+// *count = number of NaN or infinite values among f[0 .. n) (device int64).
+hipError_t launch_count_nonfinite(const float* f, size_t n, int64_t* count, hipStream_t st);
 hipError_t launch_scale(const float* in, float* out, float s, size_t n, hipStream_t st);
 // Images are float32 or bfloat16 (uint16_t bit patterns, widened exactly to
 // float32 on load); every other field is float32.

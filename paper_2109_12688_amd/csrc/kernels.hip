@@ -247,6 +247,30 @@ static int grid_for(size_t n, int threads) {
   return (int)b;
 }
 
+// Count of the entries of f that are NaN or infinite: per-wavefront sums
+// added to *count (zeroed by the first kernel, so the pair needs no memset).
+__global__ void k_zero_count(unsigned long long* count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0ull;
+}
+__global__ void k_count_nonfinite(const float* __restrict__ f, size_t n,
+                                  unsigned long long* __restrict__ count) {
+  unsigned int c = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    c += isfinite(f[i]) ? 0u : 1u;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+hipError_t launch_count_nonfinite(const float* f, size_t n, int64_t* count, hipStream_t st) {
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(count);
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, st, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0, st, f, n, cnt);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(float* p, float value, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, p, value, n);
   return hipGetLastError();

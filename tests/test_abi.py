@@ -112,6 +112,16 @@ def test_null_and_misaligned_pointers(lib):
     assert lib.nadmm_expmap(d, FAKE, 3, FAKE, FAKE, big, None) == 1  # out aliases vel
 
 
+def test_count_nonfinite_argument_checks(lib):
+    d = Dims(32, 32, 32)
+    assert lib.nadmm_count_nonfinite(d, None, 3, FAKE, None) == 1
+    assert lib.nadmm_count_nonfinite(d, FAKE, 3, None, None) == 1
+    assert lib.nadmm_count_nonfinite(d, MISALIGNED, 1, FAKE, None) == 1
+    assert lib.nadmm_count_nonfinite(d, FAKE, 0, FAKE, None) == 1
+    assert lib.nadmm_count_nonfinite(d, FAKE, 65, FAKE, None) == 1
+    assert lib.nadmm_count_nonfinite(Dims(30, 32, 32), FAKE, 1, FAKE, None) == 2
+
+
 def test_workspace_too_small(lib):
     p = _p()
     d = Dims(32, 32, 32)

@@ -224,3 +224,23 @@ def test_pyramid_vs_oracle(api):
     one = api.register_pyramid(gpu(f), gpu(m), 0.01, 0.1, 2, outer=(2,), iters=(3,))
     plain = api.register(gpu(f), gpu(m), 0.01, 0.1, 2, 2, 3)
     assert torch.equal(one["disp"], plain["disp"])
+
+
+def test_count_nonfinite(api):
+    """Exact count of NaN / +-inf entries (integer result, so exact equality):
+    none, a few at known positions (first, last, across components), and 1000
+    seeded positions in a field large enough for the grid-stride loop."""
+    d = (24, 18, 9)
+    u = synth.random_vector_field(d, seed=50, amp=1.0)
+    assert api.count_nonfinite(gpu(u)).item() == 0
+    flat = u.reshape(-1).copy()
+    bad = [0, 7, flat.size // 2, flat.size - 1]
+    for i, v in zip(bad, (np.nan, np.inf, -np.inf, np.nan)):
+        flat[i] = v
+    u2 = flat.reshape(u.shape)
+    assert api.count_nonfinite(gpu(u2)).item() == 4
+    assert [api.count_nonfinite(gpu(u2[c])).item() for c in range(3)] == [2, 1, 1]
+    big = synth.random_vector_field((128, 128, 96), seed=51, amp=1.0).reshape(-1)
+    pos = np.random.default_rng(52).choice(big.size, size=1000, replace=False)
+    big[pos] = np.nan
+    assert api.count_nonfinite(gpu(big.reshape((3, 96, 128, 128)))).item() == 1000
