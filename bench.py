@@ -77,6 +77,8 @@ def parse():
                     help="skip the gradient of one warping at 96^3")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the bfloat16-image run at 192x192x128 (vs the float32 path)")
+    ap.add_argument("--no-pyramid", action="store_true",
+                    help="skip the paper's three-level schedule on the same pair")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a device-to-device copy of known size first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -288,6 +290,36 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
             "batched_graph_vs_one_by_one": round(t_plain / t_graph, 4),
             "tile_rows": tiles,
             "bit_identical": bool(same)}
+
+
+# The paper's runtime per pair for the L2 data term with the second-order
+# regulariser (Table 1, NVIDIA V100, first hyper-parameter version): context
+# for the same schedule below, not a target (other hardware, other images).
+PAPER_V1_SECONDS = 1.38
+
+
+def pyramid_time(api, torch, pair, w, reps=5):
+    """The paper's first hyper-parameter schedule on the same phantom pair:
+    three levels, coarsest first, 10 / 10 / 5 warpings of 10 / 5 / 5 ADMM
+    iterations (nadmm_register_pyramid): ms per registration."""
+    f, m = torch.from_numpy(pair.fixed).cuda(), torch.from_numpy(pair.moving).cuda()
+    outer, iters = (10, 10, 5), (10, 5, 5)
+    ws = api.workspace_pyramid(pair.fixed.shape, outer, iters)
+    stream = torch.cuda.current_stream()
+    run = lambda: api.register_pyramid(f, m, w["lam"], w["theta"], w["order"], outer, iters, ws=ws)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps
+    log(f"pyramid (paper's first schedule): {t:.3f} ms per registration")
+    return {"levels": 3, "warpings": list(outer), "iters": list(iters), "order": "coarsest first",
+            "steps": reps, "ms_per_registration": round(t, 3),
+            "paper_v100_seconds_context": PAPER_V1_SECONDS}
 
 
 def grad_time(api, torch, synth, pair, reps=5):
@@ -512,6 +544,8 @@ def main():
         res["bf16"] = bf16_vs_plain(api, torch, synth, inputs["bf16"])
     if not args.no_grad:
         res["grad"] = grad_time(api, torch, synth, inputs["grad"])
+    if not args.no_pyramid:
+        res["pyramid"] = pyramid_time(api, torch, pair, w)
     if not args.no_batch:
         res["batch"] = batch_vs_plain(api, torch, synth,
                                       [inputs[("batch", i)] for i in range(32)])

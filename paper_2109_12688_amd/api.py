@@ -185,6 +185,14 @@ def pyramid(outer=(10, 10, 5), iters=(10, 5, 5)) -> Pyramid:
     return py
 
 
+def workspace_pyramid(vol_shape, outer=(10, 10, 5), iters=(10, 5, 5), device="cuda") -> torch.Tensor:
+    """Workspace of register_pyramid for this schedule."""
+    py = pyramid(outer, iters)
+    n = ctypes.c_size_t(0)
+    _lib.call("nadmm_workspace_size_pyramid", dims_of(vol_shape), ctypes.byref(py), ctypes.byref(n))
+    return torch.empty(int(n.value), dtype=torch.uint8, device=device)
+
+
 def register_pyramid(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
                      outer=(10, 10, 5), iters=(10, 5, 5), data_term: int = 2, eps: float = 1e-8,
                      ws: torch.Tensor | None = None) -> dict:
@@ -196,9 +204,7 @@ def register_pyramid(fixed: torch.Tensor, moving: torch.Tensor, lam: float, thet
     _check(moving, "moving", shp)
     py = pyramid(outer, iters)
     if ws is None:
-        n = ctypes.c_size_t(0)
-        _lib.call("nadmm_workspace_size_pyramid", dims_of(shp), ctypes.byref(py), ctypes.byref(n))
-        ws = torch.empty(int(n.value), dtype=torch.uint8, device=fixed.device)
+        ws = workspace_pyramid(shp, outer, iters, fixed.device)
     _check(ws, "workspace", dtype=torch.uint8)
     disp = torch.empty((3,) + shp, dtype=torch.float32, device=fixed.device)
     warped = torch.empty(shp, dtype=torch.float32, device=fixed.device)
