@@ -36,6 +36,14 @@ Readings of points the paper leaves open (each is listed in the design notes):
 * Each warping starts the ADMM loop from zero with alpha^0 = 1 (Sec. 3, text
   after Eq. (5)); the warping's velocity is the final w iterate.
 * Loop counts are fixed (Sec. 4, first hyperparameter version caps them).
+  Optionally (Sec. 4, second hyperparameter version) the loops stop at
+  thresholds whose measures the paper does not define.  Readings: the ADMM
+  loop stops after iteration k >= 1 once |s^k - s^{k-1}| <= tol |s^k|, with
+  s^k = v^k + b_hat^k the input of the w-step and |.| the L2 norm over the
+  whole vector field; the warping loop stops after warping c >= 1 (0-based:
+  from the second warping on) once |u_c - u_{c-1}| <= tol |u_c|.  Both
+  loops keep their caps.  A stopped ADMM loop returns the w^k of the
+  iteration that met the threshold.
 
 Array conventions: scalar volumes have shape (nz, ny, nx) with x fastest;
 vector fields have shape (3, nz, ny, nx) with component 0 the x displacement,
@@ -210,11 +218,28 @@ class AdmmResult:
     v: np.ndarray
     gammas: np.ndarray
     history: list = field(default_factory=list)
+    iters_run: int = 0
+    rel_change: list = field(default_factory=list)  # |s^k - s^{k-1}| / |s^k|, k >= 1
+
+
+def rel_change(new: np.ndarray, old: np.ndarray) -> float:
+    """|new - old| / |new| in the L2 norm over the whole field (0 when both
+    are zero, inf when only new is)."""
+    d, n = float(np.sum((new - old) ** 2)), float(np.sum(new ** 2))
+    if n > 0:
+        return math.sqrt(d / n)
+    return 0.0 if d == 0 else math.inf
+
+
+def below_threshold(new: np.ndarray, old: np.ndarray, tol: float) -> bool:
+    """|new - old| <= tol |new| (squared on both sides; true when both are 0)."""
+    return float(np.sum((new - old) ** 2)) <= tol * tol * float(np.sum(new ** 2))
 
 
 def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
          iters: int, data_term: int = 2, eps: float = 1e-8,
-         history: bool = False, mult: np.ndarray | None = None) -> AdmmResult:
+         history: bool = False, mult: np.ndarray | None = None,
+         tol: float | None = None) -> AdmmResult:
     """Run ``iters`` iterations (k = 0 .. iters-1) of Eq. (5) from the
     initialisation w_hat^0 = b_hat^0 = 0, alpha^0 = 1.
 
@@ -226,7 +251,9 @@ def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
       w_hat^{k+1} = w^k + (alpha^k - 1)/alpha^{k+1} (w^k - w^{k-1})
       b_hat^{k+1} = b^k + (alpha^k - 1)/alpha^{k+1} (b^k - b^{k-1})
     ``mult`` overrides the w-step multiplier (used only by tests that plant a
-    mistake to show the pins catch it)."""
+    mistake to show the pins catch it).  With ``tol`` the loop also stops
+    after the first iteration k >= 1 whose w-step input s^k = v^k + b_hat^k
+    satisfies |s^k - s^{k-1}| <= tol |s^k| (threshold stopping, Sec. 4)."""
     dims_xyz = (J.shape[3], J.shape[2], J.shape[1])
     if mult is None:
         mult = w_step_multiplier(dims_xyz, lam, theta, order)
@@ -237,14 +264,24 @@ def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
     gam = []
     hist = []
     w = b = v = zeros
+    s_prev = None
+    changes = []
+    stop = False
+    k_run = 0
     for k in range(iters):
         a = w_hat - b_hat
         if data_term == 2:
             v = v_step_l2(a, J, r, theta)
         else:
             v = v_step_l1(a, J, r, theta, eps)
-        w = fourier_solve(v + b_hat, mult)
+        s = v + b_hat
+        w = fourier_solve(s, mult)
         b = b_hat + v - w
+        k_run = k + 1
+        if tol is not None and s_prev is not None:
+            changes.append(rel_change(s, s_prev))
+            stop = below_threshold(s, s_prev, tol)
+        s_prev = s
         alpha_next = (1.0 + math.sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0
         g = (alpha - 1.0) / alpha_next
         gam.append(g)
@@ -253,11 +290,14 @@ def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
             hist.append({"v": v.copy(), "w": w.copy(), "b": b.copy(),
                          "primal": float(np.sqrt(np.sum((w - v) ** 2))),
                          "dual": float(theta * np.sqrt(np.sum((w - w_prev) ** 2)))})
+        if stop:
+            break
         w_hat = w + g * (w - w_prev)
         b_hat = b + g * (b - b_prev)
         w_prev, b_prev = w, b
         alpha = alpha_next
-    return AdmmResult(w=w, b=b, v=v, gammas=np.array(gam), history=hist)
+    return AdmmResult(w=w, b=b, v=v, gammas=np.array(gam), history=hist, iters_run=k_run,
+                      rel_change=changes)
 
 
 # ---------------------------------------------------------------------------
@@ -268,31 +308,46 @@ class RegisterResult:
     disp: np.ndarray
     warped: np.ndarray
     velocities: list
+    iters_run: list = field(default_factory=list)     # ADMM iterations of each warping
+    admm_change: list = field(default_factory=list)   # per warping: its ADMM rel_change list
+    warp_change: list = field(default_factory=list)   # |u_c - u_{c-1}| / |u_c|, c >= 1
 
 
 def register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float,
              order: int, outer: int, iters: int, data_term: int = 2,
              init_disp: np.ndarray | None = None,
-             keep_velocities: bool = False) -> RegisterResult:
+             keep_velocities: bool = False,
+             tol_admm: float | None = None, tol_warp: float | None = None) -> RegisterResult:
     """The iterative scheme of Sec. 2: solve the model for a velocity with
     the current warped source, compose it onto the deformation, warp the
     original source again, repeat ``outer`` times.
 
     Composition order (Sec. 2): phi_c = phi_{c-1} o (Id + v_c), so the
-    displacement becomes u_c(x) = v_c(x) + u_{c-1}(x + v_c(x))."""
+    displacement becomes u_c(x) = v_c(x) + u_{c-1}(x + v_c(x)).
+
+    ``tol_admm`` / ``tol_warp`` add the threshold stopping of Sec. 4's second
+    hyperparameter version (see ``admm``; the warping loop stops after
+    warping c >= 1 once |u_c - u_{c-1}| <= tol_warp |u_c|)."""
     fixed = np.asarray(fixed, dtype=np.float64)
     moving = np.asarray(moving, dtype=np.float64)
     u = np.zeros((3,) + fixed.shape) if init_disp is None else np.asarray(init_disp, np.float64).copy()
-    vels = []
-    for _ in range(outer):
+    vels, runs, achg, wchg = [], [], [], []
+    for c in range(outer):
         _, J, r = warp_grad_residual(moving, fixed, u)
-        res = admm(J, r, lam, theta, order, iters, data_term=data_term)
+        res = admm(J, r, lam, theta, order, iters, data_term=data_term, tol=tol_admm)
+        runs.append(res.iters_run)
+        achg.append(res.rel_change)
         vel = res.w
         if keep_velocities:
             vels.append(vel.copy())
-        u = compose(u, vel)
+        u_prev, u = u, compose(u, vel)
+        if tol_warp is not None and c >= 1:
+            wchg.append(rel_change(u, u_prev))
+            if below_threshold(u, u_prev, tol_warp):
+                break
     warped = trilinear_periodic(moving, u)
-    return RegisterResult(disp=u, warped=warped, velocities=vels)
+    return RegisterResult(disp=u, warped=warped, velocities=vels, iters_run=runs, admm_change=achg,
+                          warp_change=wchg)
 
 
 # ---------------------------------------------------------------------------

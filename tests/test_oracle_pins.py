@@ -563,3 +563,54 @@ def test_p20_pyramid_identity_and_levels():
     one = O.pyramid_register(f, img, 0.01, 0.1, 2, outer=(2,), iters=(3,))
     ref = O.register(f, img, 0.01, 0.1, 2, 2, 3)
     assert np.array_equal(one.disp, ref.disp)
+
+
+# ---------------------------------------------------------------------------
+# P21: threshold stopping (Sec. 4, second hyperparameter version)
+# ---------------------------------------------------------------------------
+def test_p21_admm_threshold_stops_at_first_crossing():
+    rng = np.random.default_rng(210)
+    J = 0.3 * rng.standard_normal((3, 6, 8, 10))
+    r = 0.3 * rng.standard_normal((6, 8, 10))
+    lam, theta, order, cap = 0.05, 0.1, 2, 14
+    full = O.admm(J, r, lam, theta, order, cap, history=True)
+    # the w-step input s^k = v^k + b_hat^k equals w^k + b^k (b^k = b_hat^k + v^k - w^k):
+    # its relative change, from the recorded w and b
+    s = [h["w"] + h["b"] for h in full.history]
+    rho = [np.linalg.norm(s[k] - s[k - 1]) / np.linalg.norm(s[k]) for k in range(1, cap)]
+    traced = O.admm(J, r, lam, theta, order, cap, tol=0.0)
+    assert traced.iters_run == cap
+    assert np.allclose(traced.rel_change, rho, rtol=1e-12, atol=0)
+    for pick in (2, 6, 9):
+        tol = 1.001 * rho[pick]
+        k_stop = next(k for k in range(1, cap) if rho[k - 1] <= tol)
+        res = O.admm(J, r, lam, theta, order, cap, tol=tol)
+        assert res.iters_run == k_stop + 1
+        assert np.array_equal(res.w, O.admm(J, r, lam, theta, order, k_stop + 1).w)
+    # a threshold above every change stops after the first check (k = 1)
+    assert O.admm(J, r, lam, theta, order, cap, tol=1e30).iters_run == 2
+    # zero data term: s stays exactly zero, which meets any threshold
+    z = O.admm(J, np.zeros_like(r), lam, theta, order, cap, tol=0.0)
+    assert z.iters_run == 2 and not z.w.any()
+
+
+def test_p21_warping_threshold_stops_at_first_crossing():
+    pair = synth.make_pair("blobs32")
+    f, mv = pair.fixed.astype(np.float64), pair.moving.astype(np.float64)
+    lam, theta, order, outer, iters = 0.01, 0.1, 2, 5, 4
+    # u_c for c = 0 .. outer-1 by plain registrations of c + 1 warpings
+    us = [O.register(f, mv, lam, theta, order, c + 1, iters).disp for c in range(outer)]
+    delta = [np.linalg.norm(us[c] - us[c - 1]) / np.linalg.norm(us[c]) for c in range(1, outer)]
+    traced = O.register(f, mv, lam, theta, order, outer, iters, tol_warp=0.0)
+    assert np.allclose(traced.warp_change, delta, rtol=1e-12, atol=0)
+    assert np.array_equal(traced.disp, us[-1])
+    for pick in (0, 2):
+        tol = 1.001 * delta[pick]
+        c_stop = next(c for c in range(1, outer) if delta[c - 1] <= tol)
+        res = O.register(f, mv, lam, theta, order, outer, iters, tol_warp=tol)
+        assert len(res.iters_run) == c_stop + 1
+        assert np.array_equal(res.disp, us[c_stop])
+        assert np.array_equal(res.warped, O.trilinear_periodic(mv, us[c_stop]))
+    # identical images: every field is exactly zero, both loops stop at their first check
+    same = O.register(mv, mv, lam, theta, order, outer, iters, tol_admm=0.0, tol_warp=0.0)
+    assert same.iters_run == [2, 2] and not same.disp.any()
