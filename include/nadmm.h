@@ -112,6 +112,38 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p,
                             float* velocities, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* nadmm_register with threshold stopping (Sec. 4, second hyper-parameter
+ * version: the ADMM loop ends at a convergence threshold, the warping loop
+ * once two successive warpings differ by less than a set fraction, 2 % in
+ * the paper).  The paper does not define the two measures; this library
+ * reads them as relative changes in the L2 norm over the whole field:
+ *   - ADMM: after iteration k >= 1, stop once |s^k - s^{k-1}| <= tol_admm |s^k|,
+ *     with s^k = v^k + b_hat^k the input of the w-step; the warping's
+ *     velocity is then w^k (of that iteration);
+ *   - warpings: after warping c >= 1 (0-based), stop once
+ *     |u_c - u_{c-1}| <= tol_warp |u_c|.
+ * p->iters and p->outer remain the caps.  A negative tolerance switches its
+ * check off (that loop runs to its cap); NaN is NADMM_ERR_INVALID_ARG.
+ * Sums of squares are accumulated in FP64 from the float32 fields, in an
+ * order that depends on the sizes only.
+ *   iters_run    host out, p->outer int32 or NULL: ADMM iterations of each
+ *                warping run (0 for warpings not run).
+ *   outer_run    host out or NULL: warpings run.
+ *   admm_change  host out, p->outer * (p->iters - 1) doubles or NULL: row c
+ *                holds warping c's measured changes for k = 1 .. (NaN where
+ *                not measured; the last iteration is not measured).
+ *   warp_change  host out, p->outer - 1 doubles or NULL: the change of
+ *                warping c at index c - 1 (NaN where not measured).
+ * Other arguments, the workspace (nadmm_workspace_size bytes) and errors as
+ * for nadmm_register (no initial displacement, no per-warping velocities).
+ * SYNCHRONOUS: every check waits for `stream` and reads two doubles back,
+ * and the call returns after the work is done. */
+nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, double tol_admm,
+                                      double tol_warp, const float* fixed, const float* moving,
+                                      float* disp, float* warped, int32_t* iters_run,
+                                      int32_t* outer_run, double* admm_change, double* warp_change,
+                                      void* workspace, size_t workspace_bytes, void* stream);
+
 /* nadmm_register with the two images stored as bfloat16 (each element the
  * upper 16 bits of an IEEE float32, round-to-nearest-even from the float32
  * image being the caller's job).  Image values are widened exactly to

@@ -44,6 +44,8 @@ _SIGS = {
     "nadmm_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "nadmm_last_error": ([], ctypes.c_char_p),
     "nadmm_workspace_size": ([Dims, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "nadmm_register_threshold": ([Dims, ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double, _P, _P, _P,
+                                  _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_register": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                        ctypes.c_int),
     "nadmm_register_bf16": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,

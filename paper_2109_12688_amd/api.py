@@ -105,6 +105,40 @@ def register(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float
     return res
 
 
+def register_threshold(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
+                       outer: int, iters: int, tol_admm: float, tol_warp: float, data_term: int = 2,
+                       eps: float = 1e-8, ws: torch.Tensor | None = None) -> dict:
+    """Registration with threshold stopping (nadmm_register_threshold): the
+    ADMM loop stops once |s^k - s^{k-1}| <= tol_admm |s^k|, the warping loop
+    once |u_c - u_{c-1}| <= tol_warp |u_c| (negative: no check); ``outer``
+    and ``iters`` stay the caps.  Synchronous.  Returns 'disp', 'warped',
+    'iters_run' (per warping run), 'outer_run', 'admm_change' (per warping
+    run, the changes measured: not at an iteration that ends at the cap) and
+    'warp_change' (likewise, for the warpings from the second on)."""
+    _check(fixed, "fixed")
+    shp = tuple(fixed.shape)
+    _check(moving, "moving", shp)
+    dev = fixed.device
+    disp = torch.empty((3,) + shp, dtype=torch.float32, device=dev)
+    warped = torch.empty(shp, dtype=torch.float32, device=dev)
+    ws = _ws(shp, ws, dev)
+    p = params(lam, theta, order, outer, iters, data_term, eps)
+    runs = (ctypes.c_int32 * max(outer, 1))()
+    n_run = ctypes.c_int32(0)
+    achg = (ctypes.c_double * max(outer * (iters - 1), 1))()
+    wchg = (ctypes.c_double * max(outer - 1, 1))()
+    _lib.call("nadmm_register_threshold", dims_of(shp), ctypes.byref(p), ctypes.c_double(tol_admm),
+              ctypes.c_double(tol_warp), _ptr(fixed), _ptr(moving), _ptr(disp), _ptr(warped), runs,
+              ctypes.byref(n_run), achg, wchg, _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    oc = n_run.value
+    its = [runs[c] for c in range(oc)]
+    admm_change = [[x for x in (achg[c * (iters - 1) + k] for k in range(its[c] - 1)) if x == x]
+                   for c in range(oc)]  # NaN: not measured
+    return {"disp": disp, "warped": warped, "iters_run": its, "outer_run": oc,
+            "admm_change": admm_change,
+            "warp_change": [x for x in (wchg[c] for c in range(max(oc - 1, 0))) if x == x]}
+
+
 def workspace_batch(vol_shape, batch: int, device="cuda") -> torch.Tensor:
     n = ctypes.c_size_t(0)
     _lib.call("nadmm_workspace_size_batch", dims_of(vol_shape), ctypes.c_int32(batch), ctypes.byref(n))

@@ -1,7 +1,9 @@
 // C ABI of the registration library: argument validation, workspace layout
 // and the host-side loop orchestration (Sec. 2 iterative scheme, Sec. 3
 // Eq. (5) recurrence).  All device work is enqueued on the caller's stream;
-// nothing here synchronises or allocates device memory.
+// nothing here allocates device memory, and only the threshold-stopped
+// registration (whose loop counts depend on device results) and the tile
+// autotuner synchronise.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -12,6 +14,7 @@
 
 #include "../../include/nadmm.h"
 #include "kernels.h"
+#include "reduce.h"
 
 using namespace nadmm;
 
@@ -230,11 +233,41 @@ hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const
 // J given, or (J null) recomputed in the fused pass from the warped source iw.
 // x_done: the x transform of s^0 is already in X (pass A fused with the
 // data term), so the first solve starts at pass B.
+// Threshold stopping (Sec. 4, second hyper-parameter version): a loop stops
+// after the first check at which |new - old| <= tol |new| (L2 norms over the
+// whole field; the ADMM loop compares its w-step inputs s^k, s^{k-1} from
+// k = 1 on, the warping loop the displacements u_c, u_{c-1} from c = 1 on).
+// A negative tolerance switches that loop's check off.  Every check waits
+// for the stream and reads two doubles back.
+struct StopRule {
+  double tol_admm, tol_warp;
+  double* part;          // device: 2 * kChangeBlocks doubles of scratch
+  double* admm_change;   // host, nullable: outer x (iters - 1) measured changes
+  double* warp_change;   // host, nullable: outer - 1 measured changes
+  int32_t* iters_run;    // host, nullable: ADMM iterations of each warping
+  int outer_run;
+};
+static_assert(2 * kChangeBlocks <= 4 * kJacBlocks, "change partials live in the Jacobian partials");
+
+// |a - b| / |a| and whether |a - b| <= tol |a|, over n floats.
+nadmm_status change_check(const float* a, const float* b, size_t n, double tol, double* part,
+                          hipStream_t st, double& change, bool& below) {
+  HIP_TRY(launch_change_sums(a, b, n, part, st));
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  change = h[1] > 0 ? sqrt(h[0] / h[1]) : (h[0] == 0 ? 0.0 : INFINITY);
+  below = h[0] <= tol * tol * h[1];
+  return NADMM_OK;
+}
+
 nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
                              const nadmm_params* p, const float* J, const float* iw,
                              const float* r, float*& cur, float*& prev, float2* X, float* v_last,
-                             hipStream_t st, int batch = 1, bool x_done = false) {
+                             hipStream_t st, int batch = 1, bool x_done = false,
+                             StopRule* stop = nullptr, int warping = 0) {
   const std::vector<double> gam = nesterov_gammas(p->iters);
+  if (stop && stop->iters_run) stop->iters_run[warping] = 1;
   if (x_done)
     HIP_TRY(timed(KK_PASS_B, st, [&] {
       return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch);
@@ -265,6 +298,18 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     float* tmp = cur;
     cur = prev;
     prev = tmp;
+    if (stop && stop->iters_run) stop->iters_run[warping] = k + 1;
+    if (stop && stop->tol_admm >= 0 && k + 1 < p->iters) {
+      double ch;
+      bool below;
+      CHECK(change_check(cur, prev, 3 * (size_t)g.V, stop->tol_admm, stop->part, st, ch, below));
+      if (stop->admm_change) stop->admm_change[(size_t)warping * (p->iters - 1) + (k - 1)] = ch;
+      if (below) {
+        // the solve above took the extrapolated input; redo it on s^k itself
+        HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st, batch));
+        break;
+      }
+    }
   }
   return NADMM_OK;
 }
@@ -275,7 +320,8 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
 template <typename T>
 nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, const T* moving,
                            const float* init_disp, float* disp, float* warped, float* velocities,
-                           void* workspace, size_t workspace_bytes, void* stream, int batch) {
+                           void* workspace, size_t workspace_bytes, void* stream, int batch,
+                           StopRule* stop = nullptr) {
   constexpr bool kBf16 = std::is_same<T, uint16_t>::value;
   CHECK(check_dims(d));
   CHECK(check_params(p, true));
@@ -336,7 +382,7 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
                               (float)p->eps, p->data_term, X, st, batch); }));
     float* cur = S1;
     float* prev = S2;
-    CHECK(admm_iterations(g, pl, tb, p, nullptr, iw_c, r, cur, prev, X, nullptr, st, batch, true));
+    CHECK(admm_iterations(g, pl, tb, p, nullptr, iw_c, r, cur, prev, X, nullptr, st, batch, true, stop, c));
     // final w = S s^{K-1}, composed onto the displacement
     PassCArgs a{};
     a.X = X;
@@ -347,6 +393,21 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
     a.iw_out = last ? warped : iw;
     a.vel_out = velocities ? velocities + (size_t)c * 3 * V : nullptr;
     HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_pass_c(g, pl.x, tb, kBf16 ? kComposeBf16 : kCompose, a, st, batch); }));
+    if (stop) stop->outer_run = c + 1;
+    if (stop && stop->tol_warp >= 0 && c >= 1 && !last) {
+      double ch;
+      bool below;
+      CHECK(change_check(a.out, u_src, 3 * V, stop->tol_warp, stop->part, st, ch, below));
+      if (stop->warp_change) stop->warp_change[c - 1] = ch;
+      if (below) {
+        // the buffers were laid out for `outer` warpings: this one's
+        // displacement may be in U and its warped image is in iw
+        if (a.out != disp)
+          HIP_TRY(hipMemcpyAsync(disp, a.out, 3 * V * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (warped) HIP_TRY(hipMemcpyAsync(warped, iw, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+        return NADMM_OK;
+      }
+    }
     u_src = a.out;
   }
   return NADMM_OK;
@@ -484,6 +545,34 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p, const float* fi
                             size_t workspace_bytes, void* stream) {
   return register_impl(d, p, fixed, moving, init_disp, disp, warped, velocities, workspace,
                        workspace_bytes, stream, 1);
+}
+
+nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, double tol_admm,
+                                      double tol_warp, const float* fixed, const float* moving,
+                                      float* disp, float* warped, int32_t* iters_run,
+                                      int32_t* outer_run, double* admm_change, double* warp_change,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_params(p, true));
+  if (isnan(tol_admm) || isnan(tol_warp))
+    return fail(NADMM_ERR_INVALID_ARG, "tolerances must not be NaN");
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  StopRule stop{};
+  stop.tol_admm = tol_admm;
+  stop.tol_warp = tol_warp;
+  stop.part = at<double>(workspace, layout(d).jac);
+  stop.admm_change = admm_change;
+  stop.warp_change = warp_change;
+  stop.iters_run = iters_run;
+  const int cells = p->outer * (p->iters - 1);
+  for (int i = 0; admm_change && i < cells; ++i) admm_change[i] = NAN;
+  for (int i = 0; warp_change && i + 1 < p->outer; ++i) warp_change[i] = NAN;
+  for (int i = 0; iters_run && i < p->outer; ++i) iters_run[i] = 0;
+  CHECK(register_impl(d, p, fixed, moving, nullptr, disp, warped, nullptr, workspace, workspace_bytes,
+                      stream, 1, &stop));
+  if (outer_run) *outer_run = stop.outer_run;
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  return NADMM_OK;
 }
 
 nadmm_status nadmm_register_bf16(nadmm_dims d, const nadmm_params* p, const uint16_t* fixed,

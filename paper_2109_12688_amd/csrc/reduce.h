@@ -1,0 +1,19 @@
+// Relative change of a field between two iterates, the measure of the
+// threshold stopping of Sec. 4 (second hyper-parameter version).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+
+namespace nadmm {
+
+// Most blocks of the partial pass; `part` holds 2 doubles per block.
+constexpr int kChangeBlocks = 1024;
+
+// part[0] = sum_i (a_i - b_i)^2, part[1] = sum_i a_i^2 over i < n (device
+// doubles), accumulated in FP64 in an order fixed by n alone (so repeated
+// calls give the same bits); b == nullptr reads as zero.  `part` needs
+// 2 * kChangeBlocks doubles; a and b 16-byte aligned.
+hipError_t launch_change_sums(const float* a, const float* b, size_t n, double* part, hipStream_t st);
+
+}  // namespace nadmm

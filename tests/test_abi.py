@@ -122,6 +122,24 @@ def test_count_nonfinite_argument_checks(lib):
     assert lib.nadmm_count_nonfinite(Dims(30, 32, 32), FAKE, 1, FAKE, None) == 2
 
 
+def test_register_threshold_argument_checks(lib):
+    p = _p()
+    d = Dims(32, 32, 32)
+    _, need = ws_size(lib, d)
+    n = ctypes.c_size_t(need)
+    nan, tol = ctypes.c_double(float("nan")), ctypes.c_double(0.05)
+
+    def call(d=d, ta=tol, tw=tol, fixed=FAKE, disp=FAKE, ws_bytes=n):
+        return lib.nadmm_register_threshold(d, ctypes.byref(p), ta, tw, fixed, FAKE, disp, None, None, None,
+                                            None, None, FAKE, ws_bytes, None)
+    assert call(ta=nan) == 1
+    assert call(tw=nan) == 1
+    assert call(fixed=None) == 1
+    assert call(disp=MISALIGNED) == 1
+    assert call(ws_bytes=ctypes.c_size_t(need - 1)) == 3
+    assert call(d=Dims(30, 32, 32)) == 2
+
+
 def test_workspace_too_small(lib):
     p = _p()
     d = Dims(32, 32, 32)
