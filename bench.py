@@ -77,6 +77,8 @@ def parse():
                     help="skip the gradient of one warping at 96^3")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the bfloat16-image run at 192x192x128 (vs the float32 path)")
+    ap.add_argument("--no-threshold", action="store_true",
+                    help="skip the threshold-stopped registration of the same pair")
     ap.add_argument("--no-pyramid", action="store_true",
                     help="skip the paper's three-level schedule on the same pair")
     ap.add_argument("--copy-probe", action="store_true",
@@ -322,6 +324,31 @@ def pyramid_time(api, torch, pair, w, reps=5):
             "paper_v100_seconds_context": PAPER_V1_SECONDS}
 
 
+def threshold_time(api, torch, pair, w, reps=3):
+    """Threshold stopping (nadmm_register_threshold) on the same phantom pair:
+    the ADMM loop stops at a relative change of its w-step input below
+    0.05 (the paper's thresholds range over 0.01 .. 0.13), the warping loop
+    at a displacement change below 2 %; caps 10 warpings x 40 iterations.
+    The call is synchronous (one read-back per check): wall clock."""
+    f, m = torch.from_numpy(pair.fixed).cuda(), torch.from_numpy(pair.moving).cuda()
+    ws = api.workspace(pair.fixed.shape)
+    outer, iters, ta, tw = 10, 40, 0.05, 0.02
+    run = lambda: api.register_threshold(f, m, w["lam"], w["theta"], w["order"], outer, iters, ta, tw, ws=ws)
+    res = run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = run()
+    t = (time.perf_counter() - t0) / reps * 1e3
+    n_it = sum(res["iters_run"])
+    checks = sum(len(c) for c in res["admm_change"]) + len(res["warp_change"])
+    log(f"threshold stopping: {t:.3f} ms per registration, {res['outer_run']} warpings, "
+        f"{n_it} ADMM iterations, {checks} checks")
+    return {"tol_admm": ta, "tol_warp": tw, "cap_warpings": outer, "cap_iters": iters, "steps": reps,
+            "ms_per_registration": round(t, 3), "warpings": res["outer_run"], "iters_run": res["iters_run"],
+            "admm_iterations": n_it, "checks": checks, "ms_per_admm_iter": round(t / n_it, 5)}
+
+
 def grad_time(api, torch, synth, pair, reps=5):
     """The differentiated warping at 96^3 (20 iterations, checkpoints every
     5): ms per call of the gradient entry point (loss, dL/dmoving,
@@ -546,6 +573,8 @@ def main():
         res["grad"] = grad_time(api, torch, synth, inputs["grad"])
     if not args.no_pyramid:
         res["pyramid"] = pyramid_time(api, torch, pair, w)
+    if not args.no_threshold:
+        res["threshold"] = threshold_time(api, torch, pair, w)
     if not args.no_batch:
         res["batch"] = batch_vs_plain(api, torch, synth,
                                       [inputs[("batch", i)] for i in range(32)])
