@@ -136,8 +136,12 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p,
  *                warping c at index c - 1 (NaN where not measured).
  * Other arguments, the workspace (nadmm_workspace_size bytes) and errors as
  * for nadmm_register (no initial displacement, no per-warping velocities).
- * SYNCHRONOUS: every check waits for `stream` and reads two doubles back,
- * and the call returns after the work is done. */
+ * SYNCHRONOUS: each check's two sums are read back to the host; an ADMM
+ * check is read while the next iteration already runs (on a stop that
+ * iteration is discarded and the result is the one of the stopping
+ * iteration), a warping check is waited for.  The call allocates 32 bytes
+ * of pinned host memory and two HIP events for its duration and returns
+ * after the work is done. */
 nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, double tol_admm,
                                       double tol_warp, const float* fixed, const float* moving,
                                       float* disp, float* warped, int32_t* iters_run,

@@ -237,27 +237,41 @@ hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const
 // after the first check at which |new - old| <= tol |new| (L2 norms over the
 // whole field; the ADMM loop compares its w-step inputs s^k, s^{k-1} from
 // k = 1 on, the warping loop the displacements u_c, u_{c-1} from c = 1 on).
-// A negative tolerance switches that loop's check off.  Every check waits
-// for the stream and reads two doubles back.
+// A negative tolerance switches that loop's check off.  A check's two sums
+// are copied to pinned host memory behind an event; the ADMM loop reads
+// iteration k's check while iteration k + 1 already runs (a stop at k then
+// finalises from s^k, which iteration k + 1 leaves in place), the warping
+// loop waits for its check.
 struct StopRule {
   double tol_admm, tol_warp;
-  double* part;          // device: 2 * kChangeBlocks doubles of scratch
+  double* part;          // device: kChangeScratchBytes of scratch
+  double* host;          // pinned host: 2 read-back slots of 2 doubles
+  double* host_dev;      // the same memory as the device addresses it
+  hipEvent_t ev[2];      // completion of each slot's copy
   double* admm_change;   // host, nullable: outer x (iters - 1) measured changes
   double* warp_change;   // host, nullable: outer - 1 measured changes
   int32_t* iters_run;    // host, nullable: ADMM iterations of each warping
   int outer_run;
 };
-static_assert(2 * kChangeBlocks <= 4 * kJacBlocks, "change partials live in the Jacobian partials");
+static_assert(kChangeScratchBytes <= 4 * kJacBlocks * sizeof(double),
+              "change partials live in the Jacobian partials");
 
-// |a - b| / |a| and whether |a - b| <= tol |a|, over n floats.
-nadmm_status change_check(const float* a, const float* b, size_t n, double tol, double* part,
-                          hipStream_t st, double& change, bool& below) {
-  HIP_TRY(launch_change_sums(a, b, n, part, st));
-  double h[2];
-  HIP_TRY(hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  change = h[1] > 0 ? sqrt(h[0] / h[1]) : (h[0] == 0 ? 0.0 : INFINITY);
-  below = h[0] <= tol * tol * h[1];
+// Enqueue the sums of |a - b|^2 and |a|^2 over n floats, written by the
+// kernel into read-back slot `slot` (the device partials are reused in
+// stream order).
+nadmm_status change_enqueue(const float* a, const float* b, size_t n, StopRule* stop, int slot,
+                            hipStream_t st) {
+  HIP_TRY(launch_change_sums(a, b, n, stop->part, stop->host_dev + 2 * slot, st));
+  HIP_TRY(hipEventRecord(stop->ev[slot], st));
+  return NADMM_OK;
+}
+
+// Wait for slot `slot`: |a - b| / |a| and whether |a - b| <= tol |a|.
+nadmm_status change_read(StopRule* stop, int slot, double tol, double& change, bool& below) {
+  HIP_TRY(hipEventSynchronize(stop->ev[slot]));
+  const double d = stop->host[2 * slot], n = stop->host[2 * slot + 1];
+  change = n > 0 ? sqrt(d / n) : (d == 0 ? 0.0 : INFINITY);
+  below = d <= tol * tol * n;
   return NADMM_OK;
 }
 
@@ -299,15 +313,23 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     cur = prev;
     prev = tmp;
     if (stop && stop->iters_run) stop->iters_run[warping] = k + 1;
-    if (stop && stop->tol_admm >= 0 && k + 1 < p->iters) {
-      double ch;
-      bool below;
-      CHECK(change_check(cur, prev, 3 * (size_t)g.V, stop->tol_admm, stop->part, st, ch, below));
-      if (stop->admm_change) stop->admm_change[(size_t)warping * (p->iters - 1) + (k - 1)] = ch;
-      if (below) {
-        // the solve above took the extrapolated input; redo it on s^k itself
-        HIP_TRY(spectral_ab(g, pl, tb, p, cur, nullptr, 0.0f, X, st, batch));
-        break;
+    if (stop && stop->tol_admm >= 0) {
+      // check iteration k (not the last: it ends the loop anyway), then read
+      // the check of iteration k - 1, enqueued one iteration ago
+      if (k + 1 < p->iters) CHECK(change_enqueue(cur, prev, 3 * (size_t)g.V, stop, k & 1, st));
+      if (k >= 2) {
+        double ch;
+        bool below;
+        CHECK(change_read(stop, (k - 1) & 1, stop->tol_admm, ch, below));
+        if (stop->admm_change) stop->admm_change[(size_t)warping * (p->iters - 1) + (k - 2)] = ch;
+        if (below) {
+          // stop at k - 1: iteration k (and its check) ran ahead; s^{k-1} is
+          // in prev, and the solve of pass B took an extrapolated input, so
+          // redo it on s^{k-1} itself
+          if (stop->iters_run) stop->iters_run[warping] = k;
+          HIP_TRY(spectral_ab(g, pl, tb, p, prev, nullptr, 0.0f, X, st, batch));
+          return NADMM_OK;
+        }
       }
     }
   }
@@ -397,7 +419,8 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
     if (stop && stop->tol_warp >= 0 && c >= 1 && !last) {
       double ch;
       bool below;
-      CHECK(change_check(a.out, u_src, 3 * V, stop->tol_warp, stop->part, st, ch, below));
+      CHECK(change_enqueue(a.out, u_src, 3 * V, stop, 0, st));
+      CHECK(change_read(stop, 0, stop->tol_warp, ch, below));
       if (stop->warp_change) stop->warp_change[c - 1] = ch;
       if (below) {
         // the buffers were laid out for `outer` warpings: this one's
@@ -557,10 +580,32 @@ nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, doubl
   if (isnan(tol_admm) || isnan(tol_warp))
     return fail(NADMM_ERR_INVALID_ARG, "tolerances must not be NaN");
   CHECK(check_ws(d, workspace, workspace_bytes));
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(warped, "warped", true));
+  // the read-back slots and their events live for this call only
+  struct HostRes {
+    hipStream_t st;
+    double* host = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~HostRes() {  // an early error return may leave copies in flight
+      if (host) (void)hipStreamSynchronize(st);
+      for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+      if (host) (void)hipHostFree(host);
+    }
+  } res{static_cast<hipStream_t>(stream)};
+  HIP_TRY(hipHostMalloc((void**)&res.host, 4 * sizeof(double), hipHostMallocDefault));
+  for (hipEvent_t& e : res.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   StopRule stop{};
   stop.tol_admm = tol_admm;
   stop.tol_warp = tol_warp;
   stop.part = at<double>(workspace, layout(d).jac);
+  stop.host = res.host;
+  HIP_TRY(hipHostGetDevicePointer((void**)&stop.host_dev, res.host, 0));
+  stop.ev[0] = res.ev[0];
+  stop.ev[1] = res.ev[1];
   stop.admm_change = admm_change;
   stop.warp_change = warp_change;
   stop.iters_run = iters_run;

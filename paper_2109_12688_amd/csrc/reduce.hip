@@ -1,8 +1,10 @@
 // Sums of squares for the relative change |a - b| / |a| of two iterates
 // (the measure of the threshold stopping of Sec. 4): one pass of
 // kChangeBlocks blocks writing per-block FP64 partials, then one block that
-// adds them in a fixed order.  Differences and squares are formed in FP64
-// (the difference of two float32 values is exact there).
+// adds them in a fixed order and writes the two sums where the caller reads
+// them (device memory, or mapped pinned host memory for a read-back without
+// a copy).  Differences and squares are formed in FP64 (the difference of
+// two float32 values is exact there).
 #include "reduce.h"
 
 namespace nadmm {
@@ -60,9 +62,9 @@ __global__ void __launch_bounds__(kThreads) k_change_partial(const float* __rest
   }
 }
 
-// One block: every thread adds its partials in index order, then a tree;
-// all reads happen before the barrier of block_sum2, the write after it.
-__global__ void __launch_bounds__(kThreads) k_change_final(int nb, double* part) {
+// One block adds the nb partials in index order and writes the two sums.
+__global__ void __launch_bounds__(kThreads) k_change_final(int nb, const double* __restrict__ part,
+                                                           double* out) {
   double d = 0.0, s = 0.0;
   for (int i = threadIdx.x; i < nb; i += kThreads) {
     d += part[2 * i];
@@ -70,21 +72,22 @@ __global__ void __launch_bounds__(kThreads) k_change_final(int nb, double* part)
   }
   block_sum2(d, s);
   if (threadIdx.x == 0) {
-    part[0] = d;
-    part[1] = s;
+    out[0] = d;
+    out[1] = s;
   }
 }
 
 }  // namespace
 
-hipError_t launch_change_sums(const float* a, const float* b, size_t n, double* part, hipStream_t st) {
+hipError_t launch_change_sums(const float* a, const float* b, size_t n, double* part, double* out,
+                              hipStream_t st) {
   size_t nb = (n / 4 + kThreads - 1) / kThreads;
   if (nb < 1) nb = 1;
   if (nb > (size_t)kChangeBlocks) nb = kChangeBlocks;
   hipLaunchKernelGGL(k_change_partial, dim3((unsigned)nb), dim3(kThreads), 0, st, a, b, n, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_change_final, dim3(1), dim3(kThreads), 0, st, (int)nb, part);
+  hipLaunchKernelGGL(k_change_final, dim3(1), dim3(kThreads), 0, st, (int)nb, part, out);
   return hipGetLastError();
 }
 
