@@ -19,8 +19,10 @@
  *           everywhere (resampling, finite differences and the Fourier solve).
  * Alignment. Every array pointer must be 16-byte aligned.
  * Streams.   `stream` is a hipStream_t passed as void* (NULL = the null
- *           stream).  Every call only enqueues work on that stream and
- *           returns; results are valid after the caller synchronises it.
+ *           stream).  Every call except nadmm_register_threshold and
+ *           nadmm_autotune (which wait for their own results) only enqueues
+ *           work on that stream and returns; results are valid after the
+ *           caller synchronises it.
  * Errors.   Every entry point validates all arguments before it enqueues
  *           anything, so a call that returns an error has enqueued nothing.
  *           HIP runtime failures return NADMM_ERR_HIP.  nadmm_last_error()
