@@ -44,15 +44,17 @@ def host(t):
 LAM, THETA, ORDER = 0.01, 0.1, 2
 
 
-@pytest.mark.parametrize("tol_admm,tol_warp", [(0.14, 0.065), (0.08, 0.065)])
-def test_threshold_matches_oracle(api, blobs, tol_admm, tol_warp):
+@pytest.mark.parametrize("tol_admm,tol_warp,data_term", [(0.14, 0.065, 2), (0.08, 0.065, 2), (0.11, 0.1, 1)])
+def test_threshold_matches_oracle(api, blobs, tol_admm, tol_warp, data_term):
     f, m = blobs
-    outer, iters = 8, 20
-    e = O.register(f.astype(np.float64), m.astype(np.float64), LAM, THETA, ORDER, outer, iters,
-                   tol_admm=tol_admm, tol_warp=tol_warp)
+    # L2: the blob workload's parameters; L1 (clipped v-step): those of the L1 parity test
+    lam, order, outer, iters = (LAM, ORDER, 8, 20) if data_term == 2 else (0.05, 3, 6, 16)
+    e = O.register(f.astype(np.float64), m.astype(np.float64), lam, THETA, order, outer, iters,
+                   data_term=data_term, tol_admm=tol_admm, tol_warp=tol_warp)
     assert min(abs(x / tol_admm - 1) for c in e.admm_change for x in c) > 0.01
     assert min(abs(x / tol_warp - 1) for x in e.warp_change) > 0.01
-    g = api.register_threshold(gpu(f), gpu(m), LAM, THETA, ORDER, outer, iters, tol_admm, tol_warp)
+    g = api.register_threshold(gpu(f), gpu(m), lam, THETA, order, outer, iters, tol_admm, tol_warp,
+                               data_term=data_term)
     print(f"tol {tol_admm} / {tol_warp}: iterations {g['iters_run']}, oracle {e.iters_run}", flush=True)
     assert g["outer_run"] == len(e.iters_run)
     assert g["iters_run"] == e.iters_run
