@@ -309,6 +309,7 @@ class RegisterResult:
     warped: np.ndarray
     velocities: list
     iters_run: list = field(default_factory=list)     # ADMM iterations of each warping
+    level_iters: list = field(default_factory=list)   # pyramid: iters_run of every level
     admm_change: list = field(default_factory=list)   # per warping: its ADMM rel_change list
     warp_change: list = field(default_factory=list)   # |u_c - u_{c-1}| / |u_c|, c >= 1
 
@@ -572,9 +573,13 @@ def upsample2_disp(u: np.ndarray) -> np.ndarray:
 
 
 def pyramid_register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float, order: int,
-                     outer=(10, 10, 5), iters=(10, 5, 5), data_term: int = 2) -> RegisterResult:
+                     outer=(10, 10, 5), iters=(10, 5, 5), data_term: int = 2,
+                     tol_admm: float | None = None, tol_warp: float | None = None) -> RegisterResult:
     """`register` over len(outer) levels, coarsest first, each level starting
-    from the previous level's displacement carried to its grid."""
+    from the previous level's displacement carried to its grid.  With the
+    tolerances every level stops its loops by the thresholds of `register`
+    (Sec. 4, second hyperparameter version: the pyramid with threshold
+    stopping), outer and iters being the caps."""
     levels = len(outer)
     fs = [np.asarray(fixed, np.float64)]
     ms = [np.asarray(moving, np.float64)]
@@ -583,9 +588,12 @@ def pyramid_register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: f
         ms.insert(0, downsample2(ms[0]))
     u = None
     res = None
+    runs = []
     for lv in range(levels):
         init = None if u is None else upsample2_disp(u)
         res = register(fs[lv], ms[lv], lam, theta, order, outer[lv], iters[lv], data_term=data_term,
-                       init_disp=init)
+                       init_disp=init, tol_admm=tol_admm, tol_warp=tol_warp)
+        runs.append(res.iters_run)
         u = res.disp
+    res.level_iters = runs
     return res

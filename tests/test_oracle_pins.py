@@ -614,3 +614,20 @@ def test_p21_warping_threshold_stops_at_first_crossing():
     # identical images: every field is exactly zero, both loops stop at their first check
     same = O.register(mv, mv, lam, theta, order, outer, iters, tol_admm=0.0, tol_warp=0.0)
     assert same.iters_run == [2, 2] and not same.disp.any()
+
+
+def test_p21_pyramid_with_thresholds():
+    d = (32, 24, 16)
+    f = synth.random_volume(d, seed=211, smooth_kmax=2).astype(np.float64)
+    m = synth.random_volume(d, seed=212, smooth_kmax=2).astype(np.float64)
+    outer, iters = (3, 3, 2), (4, 3, 3)
+    plain = O.pyramid_register(f, m, 0.01, 0.1, 2, outer, iters)
+    # thresholds no change reaches: the capped schedule, bit for bit
+    never = O.pyramid_register(f, m, 0.01, 0.1, 2, outer, iters, tol_admm=0.0, tol_warp=0.0)
+    assert np.array_equal(never.disp, plain.disp)
+    assert never.level_iters == [[4, 4, 4], [3, 3, 3], [3, 3]]
+    # thresholds every change meets: two warpings of two iterations per level
+    first = O.pyramid_register(f, m, 0.01, 0.1, 2, outer, iters, tol_admm=1e30, tol_warp=1e30)
+    assert first.level_iters == [[2, 2], [2, 2], [2, 2]]
+    ref = O.pyramid_register(f, m, 0.01, 0.1, 2, (2, 2, 2), (2, 2, 2))
+    assert np.array_equal(first.disp, ref.disp)
