@@ -19,8 +19,9 @@
  *           everywhere (resampling, finite differences and the Fourier solve).
  * Alignment. Every array pointer must be 16-byte aligned.
  * Streams.   `stream` is a hipStream_t passed as void* (NULL = the null
- *           stream).  Every call except nadmm_register_threshold and
- *           nadmm_autotune (which wait for their own results) only enqueues
+ *           stream).  Every call except nadmm_register_threshold,
+ *           nadmm_register_pyramid_threshold and nadmm_autotune (which wait
+ *           for their own results) only enqueues
  *           work on that stream and returns; results are valid after the
  *           caller synchronises it.
  * Errors.   Every entry point validates all arguments before it enqueues
@@ -202,6 +203,26 @@ nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const n
                                     const float* fixed, const float* moving, float* disp,
                                     float* warped, void* workspace, size_t workspace_bytes,
                                     void* stream);
+
+/* The pyramid with threshold stopping at every level (Sec. 4, second
+ * hyper-parameter version: the three-level scheme with the ADMM and warping
+ * loops ended by thresholds; measures and rules as for
+ * nadmm_register_threshold, pyr->outer / pyr->iters being the caps).
+ *   iters_run  host out or NULL: sum of pyr->outer[l] int32; level l's
+ *              warpings start at index outer[0] + .. + outer[l-1] and hold
+ *              the ADMM iterations run (0 for warpings not run).
+ *   outer_run  host out or NULL: pyr->levels int32, warpings run per level.
+ * Other arguments, workspace and errors as for nadmm_register_pyramid
+ * (NaN tolerances: NADMM_ERR_INVALID_ARG).  Synchronous, and allocates 32
+ * bytes of pinned host memory and two events for its duration, as
+ * nadmm_register_threshold does. */
+nadmm_status nadmm_register_pyramid_threshold(nadmm_dims d, const nadmm_params* p,
+                                              const nadmm_pyramid* pyr, double tol_admm,
+                                              double tol_warp, const float* fixed,
+                                              const float* moving, float* disp, float* warped,
+                                              int32_t* iters_run, int32_t* outer_run,
+                                              void* workspace, size_t workspace_bytes,
+                                              void* stream);
 
 /* Tile autotuner: times the fused x-line pass of the iteration for every
  * admissible number of y rows per workgroup (even divisors of ny up to 32

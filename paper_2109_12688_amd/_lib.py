@@ -63,6 +63,9 @@ _SIGS = {
                                      ctypes.c_int),
     "nadmm_register_pyramid": ([Dims, ctypes.POINTER(Params), ctypes.POINTER(Pyramid), _P, _P, _P, _P, _P,
                                 ctypes.c_size_t, _P], ctypes.c_int),
+    "nadmm_register_pyramid_threshold": ([Dims, ctypes.POINTER(Params), ctypes.POINTER(Pyramid), ctypes.c_double,
+                                          ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
+                                         ctypes.c_int),
     "nadmm_admm": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_fourier_solve": ([Dims, ctypes.POINTER(Params), _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_warp": ([Dims, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),

@@ -248,6 +248,35 @@ def register_pyramid(fixed: torch.Tensor, moving: torch.Tensor, lam: float, thet
     return {"disp": disp, "warped": warped}
 
 
+def register_pyramid_threshold(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
+                               outer, iters, tol_admm: float, tol_warp: float, data_term: int = 2,
+                               eps: float = 1e-8, ws: torch.Tensor | None = None) -> dict:
+    """The pyramid with threshold stopping at every level
+    (nadmm_register_pyramid_threshold; ``outer`` / ``iters`` per level are
+    the caps).  Synchronous.  Returns 'disp', 'warped', 'level_iters' (per
+    level, the ADMM iterations of each warping run) and 'outer_run'."""
+    _check(fixed, "fixed")
+    shp = tuple(fixed.shape)
+    _check(moving, "moving", shp)
+    py = pyramid(outer, iters)
+    if ws is None:
+        ws = workspace_pyramid(shp, outer, iters, fixed.device)
+    _check(ws, "workspace", dtype=torch.uint8)
+    disp = torch.empty((3,) + shp, dtype=torch.float32, device=fixed.device)
+    warped = torch.empty(shp, dtype=torch.float32, device=fixed.device)
+    p = params(lam, theta, order, 1, 1, data_term, eps)
+    runs = (ctypes.c_int32 * max(sum(outer), 1))()
+    oruns = (ctypes.c_int32 * len(outer))()
+    _lib.call("nadmm_register_pyramid_threshold", dims_of(shp), ctypes.byref(p), ctypes.byref(py),
+              ctypes.c_double(tol_admm), ctypes.c_double(tol_warp), _ptr(fixed), _ptr(moving), _ptr(disp),
+              _ptr(warped), runs, oruns, _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    level_iters, at = [], 0
+    for lv, n in enumerate(outer):
+        level_iters.append([runs[at + c] for c in range(oruns[lv])])
+        at += n
+    return {"disp": disp, "warped": warped, "level_iters": level_iters, "outer_run": list(oruns)}
+
+
 def autotune(vol_shape, lam: float, theta: float, order: int, batch: int = 1,
              ws: torch.Tensor | None = None, device="cuda") -> int:
     """Pick and keep the fastest x-line tile for these sizes (see

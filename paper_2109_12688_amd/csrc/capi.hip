@@ -275,6 +275,31 @@ nadmm_status change_read(StopRule* stop, int slot, double tol, double& change, b
   return NADMM_OK;
 }
 
+// Pinned read-back slots and their events, for one threshold-stopped call
+// (released when it returns; an early error return may leave a write in
+// flight, so the stream is drained first).
+struct CheckHost {
+  hipStream_t st;
+  double* host = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~CheckHost() {
+    if (host) (void)hipStreamSynchronize(st);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (host) (void)hipHostFree(host);
+  }
+  // Allocates the slots and events and points `stop` at them.
+  nadmm_status init(StopRule& stop) {
+    HIP_TRY(hipHostMalloc((void**)&host, 4 * sizeof(double), hipHostMallocDefault));
+    for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    stop.host = host;
+    HIP_TRY(hipHostGetDevicePointer((void**)&stop.host_dev, host, 0));
+    stop.ev[0] = ev[0];
+    stop.ev[1] = ev[1];
+    return NADMM_OK;
+  }
+};
+
 nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
                              const nadmm_params* p, const float* J, const float* iw,
                              const float* r, float*& cur, float*& prev, float2* X, float* v_last,
@@ -584,28 +609,12 @@ nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, doubl
   CHECK(check_ptr(moving, "moving", false));
   CHECK(check_ptr(disp, "disp", false));
   CHECK(check_ptr(warped, "warped", true));
-  // the read-back slots and their events live for this call only
-  struct HostRes {
-    hipStream_t st;
-    double* host = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    ~HostRes() {  // an early error return may leave copies in flight
-      if (host) (void)hipStreamSynchronize(st);
-      for (hipEvent_t e : ev)
-        if (e) (void)hipEventDestroy(e);
-      if (host) (void)hipHostFree(host);
-    }
-  } res{static_cast<hipStream_t>(stream)};
-  HIP_TRY(hipHostMalloc((void**)&res.host, 4 * sizeof(double), hipHostMallocDefault));
-  for (hipEvent_t& e : res.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   StopRule stop{};
+  CheckHost res{static_cast<hipStream_t>(stream)};
+  CHECK(res.init(stop));
   stop.tol_admm = tol_admm;
   stop.tol_warp = tol_warp;
   stop.part = at<double>(workspace, layout(d).jac);
-  stop.host = res.host;
-  HIP_TRY(hipHostGetDevicePointer((void**)&stop.host_dev, res.host, 0));
-  stop.ev[0] = res.ev[0];
-  stop.ev[1] = res.ev[1];
   stop.admm_change = admm_change;
   stop.warp_change = warp_change;
   stop.iters_run = iters_run;
@@ -715,10 +724,13 @@ nadmm_status nadmm_workspace_size_pyramid(nadmm_dims d, const nadmm_pyramid* pyr
   return NADMM_OK;
 }
 
-nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const nadmm_pyramid* pyr,
-                                    const float* fixed, const float* moving, float* disp,
-                                    float* warped, void* workspace, size_t workspace_bytes,
-                                    void* stream) {
+// The pyramid of nadmm_register_pyramid; `stop` (nullable) adds threshold
+// stopping at every level, with iters_run / outer_run (host, nullable) laid
+// out as nadmm_register_pyramid_threshold documents.
+nadmm_status pyramid_impl(nadmm_dims d, const nadmm_params* p, const nadmm_pyramid* pyr,
+                          const float* fixed, const float* moving, float* disp, float* warped,
+                          void* workspace, size_t workspace_bytes, void* stream, StopRule* stop,
+                          int32_t* iters_run, int32_t* outer_run) {
   CHECK(check_dims(d));
   CHECK(check_pyramid(d, pyr));
   CHECK(check_params(p, false));
@@ -750,6 +762,7 @@ nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const n
   }
   const size_t reg_bytes = PL.img[0] - PL.reg;  // == layout(d).total (rounded)
   const float* u_prev = nullptr;
+  int run_at = 0;
   for (int l = 0; l < L; ++l) {
     const nadmm_dims dl = level_dims(d, L, l);
     const float* init = nullptr;
@@ -762,11 +775,61 @@ nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const n
     nadmm_params pl = *p;
     pl.outer = pyr->outer[l];
     pl.iters = pyr->iters[l];
+    if (stop) {
+      stop->part = at<double>(at<char>(workspace, PL.reg), layout(dl).jac);
+      stop->iters_run = iters_run ? iters_run + run_at : nullptr;
+      stop->outer_run = 0;
+    }
     CHECK(register_impl(dl, &pl, F[l], M[l], init, out, l == L - 1 ? warped : nullptr, nullptr,
                         at<char>(workspace, PL.reg), L > 1 ? reg_bytes : workspace_bytes, stream,
-                        1));
+                        1, stop));
+    if (stop && outer_run) outer_run[l] = stop->outer_run;
+    run_at += pyr->outer[l];
     u_prev = out;
   }
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const nadmm_pyramid* pyr,
+                                    const float* fixed, const float* moving, float* disp,
+                                    float* warped, void* workspace, size_t workspace_bytes,
+                                    void* stream) {
+  return pyramid_impl(d, p, pyr, fixed, moving, disp, warped, workspace, workspace_bytes, stream,
+                      nullptr, nullptr, nullptr);
+}
+
+nadmm_status nadmm_register_pyramid_threshold(nadmm_dims d, const nadmm_params* p,
+                                              const nadmm_pyramid* pyr, double tol_admm,
+                                              double tol_warp, const float* fixed,
+                                              const float* moving, float* disp, float* warped,
+                                              int32_t* iters_run, int32_t* outer_run,
+                                              void* workspace, size_t workspace_bytes,
+                                              void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_pyramid(d, pyr));
+  CHECK(check_params(p, false));
+  if (isnan(tol_admm) || isnan(tol_warp))
+    return fail(NADMM_ERR_INVALID_ARG, "tolerances must not be NaN");
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(warped, "warped", true));
+  CHECK(check_ptr(workspace, "workspace", false));
+  if (workspace_bytes < pyr_layout(d, pyr->levels).total)
+    return fail(NADMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                workspace_bytes, pyr_layout(d, pyr->levels).total);
+  int total = 0;
+  for (int l = 0; l < pyr->levels; ++l) total += pyr->outer[l];
+  for (int i = 0; iters_run && i < total; ++i) iters_run[i] = 0;
+  for (int l = 0; outer_run && l < pyr->levels; ++l) outer_run[l] = 0;
+  StopRule stop{};
+  CheckHost res{static_cast<hipStream_t>(stream)};
+  CHECK(res.init(stop));
+  stop.tol_admm = tol_admm;
+  stop.tol_warp = tol_warp;
+  CHECK(pyramid_impl(d, p, pyr, fixed, moving, disp, warped, workspace, workspace_bytes, stream, &stop,
+                     iters_run, outer_run));
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
   return NADMM_OK;
 }
 

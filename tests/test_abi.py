@@ -140,6 +140,27 @@ def test_register_threshold_argument_checks(lib):
     assert call(d=Dims(30, 32, 32)) == 2
 
 
+def test_register_pyramid_threshold_argument_checks(lib):
+    p = _p()
+    d = Dims(32, 32, 32)
+    py = _lib.Pyramid(3, (2, 2, 1, 0), (3, 2, 2, 0))
+    need = ctypes.c_size_t(0)
+    assert lib.nadmm_workspace_size_pyramid(d, ctypes.byref(py), ctypes.byref(need)) == 0
+    n = ctypes.c_size_t(need.value)
+    nan, tol = ctypes.c_double(float("nan")), ctypes.c_double(0.05)
+
+    def call(d=d, pyr=py, ta=tol, fixed=FAKE, ws_bytes=n):
+        return lib.nadmm_register_pyramid_threshold(d, ctypes.byref(p), ctypes.byref(pyr) if pyr else None, ta,
+                                                    tol, fixed, FAKE, FAKE, None, None, None, FAKE, ws_bytes,
+                                                    None)
+    assert call(ta=nan) == 1
+    assert call(fixed=None) == 1
+    assert call(pyr=None) == 1
+    assert call(ws_bytes=ctypes.c_size_t(need.value - 1)) == 3
+    bad = _lib.Pyramid(5, (1, 1, 1, 1), (1, 1, 1, 1))
+    assert call(pyr=bad) == 1
+
+
 def test_workspace_too_small(lib):
     p = _p()
     d = Dims(32, 32, 32)

@@ -117,3 +117,38 @@ def test_threshold_full_size_decisions_are_consistent(api):
     else:
         assert len(wc) == outer - 2 and all(x > tw for x in wc)
     assert torch.isfinite(g["disp"]).all()
+
+
+def test_pyramid_threshold_matches_oracle(api, blobs, monkeypatch):
+    """Three levels (8^3, 16^3, 32^3) with threshold stopping at every level:
+    loop counts per level exactly, displacement and warped image to the
+    registration tolerances."""
+    import oracle.nadmm_ref as R
+    f, m = blobs
+    outer, iters, ta, tw = (6, 6, 4), (16, 12, 12), 0.11, 0.08
+    levels = []
+    plain = R.register
+
+    def recording(*a, **k):
+        levels.append(plain(*a, **k))
+        return levels[-1]
+    monkeypatch.setattr(R, "register", recording)
+    e = R.pyramid_register(f.astype(np.float64), m.astype(np.float64), LAM, THETA, ORDER, outer, iters,
+                           tol_admm=ta, tol_warp=tw)
+    assert min(abs(x / ta - 1) for r in levels for c in r.admm_change for x in c) > 0.01
+    assert min(abs(x / tw - 1) for r in levels for x in r.warp_change) > 0.01
+    g = api.register_pyramid_threshold(gpu(f), gpu(m), LAM, THETA, ORDER, outer, iters, ta, tw)
+    print(f"pyramid: iterations {g['level_iters']}, oracle {e.level_iters}", flush=True)
+    assert g["level_iters"] == e.level_iters
+    assert g["outer_run"] == [len(x) for x in e.level_iters]
+    assert np.abs(host(g["disp"]) - e.disp).max() < 1e-3
+    assert np.abs(host(g["warped"]) - e.warped).max() < 1e-4
+
+
+def test_pyramid_threshold_off_is_the_pyramid(api, blobs):
+    f, m = blobs
+    outer, iters = (2, 2, 1), (4, 3, 3)
+    g = api.register_pyramid_threshold(gpu(f), gpu(m), LAM, THETA, ORDER, outer, iters, -1.0, -1.0)
+    ref = api.register_pyramid(gpu(f), gpu(m), LAM, THETA, ORDER, outer, iters)
+    assert g["level_iters"] == [[4, 4], [3, 3], [3]] and g["outer_run"] == [2, 2, 1]
+    assert torch.equal(g["disp"], ref["disp"]) and torch.equal(g["warped"], ref["warped"])
