@@ -450,8 +450,8 @@ def main():
                                                            args.workload, kind)))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
-              "part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): registrations would shard "
+              "by pair over several GPUs, which this benchmark does not run", file=sys.stderr)
         sys.exit(2)
     import numpy as np
 
