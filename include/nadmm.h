@@ -139,12 +139,13 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p,
  *                warping c at index c - 1 (NaN where not measured).
  * Other arguments, the workspace (nadmm_workspace_size bytes) and errors as
  * for nadmm_register (no initial displacement, no per-warping velocities).
- * SYNCHRONOUS: each check's two sums are read back to the host; an ADMM
- * check is read while the next iteration already runs (on a stop that
- * iteration is discarded and the result is the one of the stopping
- * iteration), a warping check is waited for.  The call allocates 32 bytes
- * of pinned host memory and two HIP events for its duration and returns
- * after the work is done. */
+ * SYNCHRONOUS: each check's per-block partial sums (at most 1024 pairs of
+ * doubles) are written into pinned host memory and added there in block
+ * order; an ADMM check is read while the next iteration already runs (on a
+ * stop that iteration is discarded and the result is the one of the
+ * stopping iteration), a warping check is waited for.  The call allocates
+ * 32 KB of pinned host memory and two HIP events for its duration and
+ * returns after the work is done. */
 nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, double tol_admm,
                                       double tol_warp, const float* fixed, const float* moving,
                                       float* disp, float* warped, int32_t* iters_run,
@@ -214,7 +215,7 @@ nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const n
  *   outer_run  host out or NULL: pyr->levels int32, warpings run per level.
  * Other arguments, workspace and errors as for nadmm_register_pyramid
  * (NaN tolerances: NADMM_ERR_INVALID_ARG).  Synchronous, and allocates 32
- * bytes of pinned host memory and two events for its duration, as
+ * KB of pinned host memory and two events for its duration, as
  * nadmm_register_threshold does. */
 nadmm_status nadmm_register_pyramid_threshold(nadmm_dims d, const nadmm_params* p,
                                               const nadmm_pyramid* pyr, double tol_admm,

@@ -237,39 +237,43 @@ hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const
 // after the first check at which |new - old| <= tol |new| (L2 norms over the
 // whole field; the ADMM loop compares its w-step inputs s^k, s^{k-1} from
 // k = 1 on, the warping loop the displacements u_c, u_{c-1} from c = 1 on).
-// A negative tolerance switches that loop's check off.  A check's two sums
-// are copied to pinned host memory behind an event; the ADMM loop reads
-// iteration k's check while iteration k + 1 already runs (a stop at k then
-// finalises from s^k, which iteration k + 1 leaves in place), the warping
-// loop waits for its check.
+// A negative tolerance switches that loop's check off.  A check's per-block
+// partial sums are written into pinned host memory behind an event and
+// added there in block order; the ADMM loop reads iteration k's check while
+// iteration k + 1 already runs (a stop at k then finalises from s^k, which
+// iteration k + 1 leaves in place), the warping loop waits for its check.
+constexpr int kSlotDoubles = 2 * kChangeBlocks;
 struct StopRule {
   double tol_admm, tol_warp;
-  double* part;          // device: kChangeScratchBytes of scratch
-  double* host;          // pinned host: 2 read-back slots of 2 doubles
+  double* host;          // pinned host: 2 read-back slots of kSlotDoubles
   double* host_dev;      // the same memory as the device addresses it
+  int nb[2];             // blocks of the check in each slot
   hipEvent_t ev[2];      // completion of each slot's copy
   double* admm_change;   // host, nullable: outer x (iters - 1) measured changes
   double* warp_change;   // host, nullable: outer - 1 measured changes
   int32_t* iters_run;    // host, nullable: ADMM iterations of each warping
   int outer_run;
 };
-static_assert(kChangeScratchBytes <= 4 * kJacBlocks * sizeof(double),
-              "change partials live in the Jacobian partials");
-
-// Enqueue the sums of |a - b|^2 and |a|^2 over n floats, written by the
-// kernel into read-back slot `slot` (the device partials are reused in
-// stream order).
+// Enqueue the partial sums of |a - b|^2 and |a|^2 over n floats, written by
+// the kernel into read-back slot `slot`.
 nadmm_status change_enqueue(const float* a, const float* b, size_t n, StopRule* stop, int slot,
                             hipStream_t st) {
-  HIP_TRY(launch_change_sums(a, b, n, stop->part, stop->host_dev + 2 * slot, st));
+  stop->nb[slot] = change_blocks(n);
+  HIP_TRY(launch_change_partials(a, b, n, stop->host_dev + (size_t)kSlotDoubles * slot, st));
   HIP_TRY(hipEventRecord(stop->ev[slot], st));
   return NADMM_OK;
 }
 
-// Wait for slot `slot`: |a - b| / |a| and whether |a - b| <= tol |a|.
+// Wait for slot `slot` and add its partials in block order: |a - b| / |a|
+// and whether |a - b| <= tol |a|.
 nadmm_status change_read(StopRule* stop, int slot, double tol, double& change, bool& below) {
   HIP_TRY(hipEventSynchronize(stop->ev[slot]));
-  const double d = stop->host[2 * slot], n = stop->host[2 * slot + 1];
+  const double* part = stop->host + (size_t)kSlotDoubles * slot;
+  double d = 0.0, n = 0.0;
+  for (int j = 0; j < stop->nb[slot]; ++j) {
+    d += part[2 * j];
+    n += part[2 * j + 1];
+  }
   change = n > 0 ? sqrt(d / n) : (d == 0 ? 0.0 : INFINITY);
   below = d <= tol * tol * n;
   return NADMM_OK;
@@ -290,7 +294,7 @@ struct CheckHost {
   }
   // Allocates the slots and events and points `stop` at them.
   nadmm_status init(StopRule& stop) {
-    HIP_TRY(hipHostMalloc((void**)&host, 4 * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&host, 2 * kSlotDoubles * sizeof(double), hipHostMallocDefault));
     for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     stop.host = host;
     HIP_TRY(hipHostGetDevicePointer((void**)&stop.host_dev, host, 0));
@@ -614,7 +618,6 @@ nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, doubl
   CHECK(res.init(stop));
   stop.tol_admm = tol_admm;
   stop.tol_warp = tol_warp;
-  stop.part = at<double>(workspace, layout(d).jac);
   stop.admm_change = admm_change;
   stop.warp_change = warp_change;
   stop.iters_run = iters_run;
@@ -776,7 +779,6 @@ nadmm_status pyramid_impl(nadmm_dims d, const nadmm_params* p, const nadmm_pyram
     pl.outer = pyr->outer[l];
     pl.iters = pyr->iters[l];
     if (stop) {
-      stop->part = at<double>(at<char>(workspace, PL.reg), layout(dl).jac);
       stop->iters_run = iters_run ? iters_run + run_at : nullptr;
       stop->outer_run = 0;
     }

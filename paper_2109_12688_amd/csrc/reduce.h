@@ -7,16 +7,18 @@
 
 namespace nadmm {
 
-// Most blocks of the partial pass; `part` holds 2 doubles per block.
+// Most blocks of the pass; the partials are 2 doubles per block.
 constexpr int kChangeBlocks = 1024;
-constexpr size_t kChangeScratchBytes = 2 * kChangeBlocks * sizeof(double);
 
-// out[0] = sum_i (a_i - b_i)^2, out[1] = sum_i a_i^2 over i < n, accumulated
-// in FP64 in an order fixed by n alone (repeated calls give the same bits);
-// b == nullptr reads as zero.  `part` is kChangeScratchBytes of device
-// scratch; `out` is device memory or mapped pinned host memory; a and b
-// 16-byte aligned.  Calls sharing `part` must be stream-ordered.
-hipError_t launch_change_sums(const float* a, const float* b, size_t n, double* part, double* out,
-                              hipStream_t st);
+// Blocks the pass uses for n floats (at most kChangeBlocks).
+int change_blocks(size_t n);
+
+// Per-block partial sums of (a_i - b_i)^2 and a_i^2 over i < n, formed in
+// FP64: part[2 j] and part[2 j + 1] for block j < change_blocks(n), each
+// block's share of the indices fixed by n alone.  b == nullptr reads as
+// zero.  `part` is device memory or mapped pinned host memory (the reader
+// adds the partials in index order, so repeated calls give the same bits);
+// a and b 16-byte aligned.
+hipError_t launch_change_partials(const float* a, const float* b, size_t n, double* part, hipStream_t st);
 
 }  // namespace nadmm

@@ -1,10 +1,9 @@
 // Sums of squares for the relative change |a - b| / |a| of two iterates
-// (the measure of the threshold stopping of Sec. 4): one pass of
-// kChangeBlocks blocks writing per-block FP64 partials, then one block that
-// adds them in a fixed order and writes the two sums where the caller reads
-// them (device memory, or mapped pinned host memory for a read-back without
-// a copy).  Differences and squares are formed in FP64 (the difference of
-// two float32 values is exact there).
+// (the measure of the threshold stopping of Sec. 4): one pass of up to
+// kChangeBlocks blocks, each writing its FP64 partial sums where the caller
+// reads them (mapped pinned host memory: no copy and no second launch).
+// Differences and squares are formed in FP64 (the difference of two
+// float32 values is exact there).
 #include "reduce.h"
 
 namespace nadmm {
@@ -38,7 +37,7 @@ __device__ inline void acc(double& d, double& s, float x, float y) {
 
 __global__ void __launch_bounds__(kThreads) k_change_partial(const float* __restrict__ a,
                                                              const float* __restrict__ b, size_t n,
-                                                             double* __restrict__ part) {
+                                                             double* part) {
   double d = 0.0, s = 0.0;
   const size_t n4 = n / 4, stride = (size_t)gridDim.x * kThreads;
   const float4* a4 = reinterpret_cast<const float4*>(a);
@@ -62,32 +61,15 @@ __global__ void __launch_bounds__(kThreads) k_change_partial(const float* __rest
   }
 }
 
-// One block adds the nb partials in index order and writes the two sums.
-__global__ void __launch_bounds__(kThreads) k_change_final(int nb, const double* __restrict__ part,
-                                                           double* out) {
-  double d = 0.0, s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kThreads) {
-    d += part[2 * i];
-    s += part[2 * i + 1];
-  }
-  block_sum2(d, s);
-  if (threadIdx.x == 0) {
-    out[0] = d;
-    out[1] = s;
-  }
-}
-
 }  // namespace
 
-hipError_t launch_change_sums(const float* a, const float* b, size_t n, double* part, double* out,
-                              hipStream_t st) {
-  size_t nb = (n / 4 + kThreads - 1) / kThreads;
-  if (nb < 1) nb = 1;
-  if (nb > (size_t)kChangeBlocks) nb = kChangeBlocks;
-  hipLaunchKernelGGL(k_change_partial, dim3((unsigned)nb), dim3(kThreads), 0, st, a, b, n, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_change_final, dim3(1), dim3(kThreads), 0, st, (int)nb, part, out);
+int change_blocks(size_t n) {
+  const size_t nb = (n / 4 + kThreads - 1) / kThreads;
+  return nb < 1 ? 1 : (nb > (size_t)kChangeBlocks ? kChangeBlocks : (int)nb);
+}
+
+hipError_t launch_change_partials(const float* a, const float* b, size_t n, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_change_partial, dim3((unsigned)change_blocks(n)), dim3(kThreads), 0, st, a, b, n, part);
   return hipGetLastError();
 }
 
