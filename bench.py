@@ -154,7 +154,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pair, w):
+def cpu_baseline(pair, w, extra=None):
     """The FP64 oracle on a bounded sample: one warping (warp, gradient,
     `iters` ADMM iterations, composition) of the same workload, scaled to
     registrations/s (a registration is `outer` such warpings)."""
@@ -172,9 +172,42 @@ def cpu_baseline(pair, w):
         res = O.admm(J, r, w["lam"], w["theta"], w["order"], w["iters"])
         O.compose(u, res.w)
         dt = time.perf_counter() - t0
-    return {"value": 1.0 / (w["outer"] * dt), "unit": "registrations/s", "cores": 1, "kind": "oracle",
-            "sample": f"one warping ({w['iters']} ADMM iterations + warp + compose) of {w['outer']}, "
-                      f"numpy float64 single thread, {dt:.2f} s"}
+    out = {"value": 1.0 / (w["outer"] * dt), "unit": "registrations/s", "cores": 1, "kind": "oracle",
+           "sample": f"one warping ({w['iters']} ADMM iterations + warp + compose) of {w['outer']}, "
+                     f"numpy float64 single thread, {dt:.2f} s"}
+    out["s_per_admm_iter"] = round(dt / w["iters"], 4)
+    out["others"] = cpu_others(extra or {})
+    return out
+
+
+def cpu_others(pairs):
+    """The oracle, single-threaded, on the other workloads' bounded samples:
+    the whole 32^3 blob registration (5 warpings x 10 iterations), and three
+    ADMM iterations of the 192 x 192 x 128 phantom (per iteration)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    import synth
+
+    res = {}
+    with threadpool_limits(limits=1):
+        wb = synth.WORKLOADS["blobs32"]
+        pb = synth.make_pair("blobs32")
+        t0 = time.perf_counter()
+        O.register(pb.fixed.astype(np.float64), pb.moving.astype(np.float64), wb["lam"], wb["theta"],
+                   wb["order"], wb["outer"], wb["iters"])
+        dt = time.perf_counter() - t0
+        res["blobs32"] = {"s_per_registration": round(dt, 3),
+                          "s_per_admm_iter": round(dt / (wb["outer"] * wb["iters"]), 5)}
+        if "phantom192x192x128" in pairs:
+            p, w2 = pairs["phantom192x192x128"], synth.WORKLOADS["phantom192x192x128"]
+            _, J, r = O.warp_grad_residual(p.moving.astype(np.float64), p.fixed.astype(np.float64),
+                                           np.zeros((3,) + p.fixed.shape))
+            t0 = time.perf_counter()
+            O.admm(J, r, w2["lam"], w2["theta"], w2["order"], 3)
+            res["phantom192x192x128"] = {"s_per_admm_iter": round((time.perf_counter() - t0) / 3, 4)}
+    return res
 
 
 def generate_inputs(args):
@@ -602,7 +635,8 @@ def main():
                                       [inputs[("batch", i)] for i in range(32)])
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the CPU")
-        res["cpu_baseline"] = cpu_baseline(pair, w)
+        res["cpu_baseline"] = cpu_baseline(pair, w, {"phantom192x192x128": inputs["bf16"]} if "bf16" in inputs
+                                           else None)
     print(json.dumps(res), flush=True)
 
 
