@@ -233,6 +233,8 @@ hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const
 // J given, or (J null) recomputed in the fused pass from the warped source iw.
 // x_done: the x transform of s^0 is already in X (pass A fused with the
 // data term), so the first solve starts at pass B.
+// stop (nullable): threshold stopping; the loop may then end early, with X
+// holding the pass-B output for S applied to the stopping iterate.
 // Threshold stopping (Sec. 4, second hyper-parameter version): a loop stops
 // after the first check at which |new - old| <= tol |new| (L2 norms over the
 // whole field; the ADMM loop compares its w-step inputs s^k, s^{k-1} from
@@ -248,12 +250,13 @@ struct StopRule {
   double* host;          // pinned host: 2 read-back slots of kSlotDoubles
   double* host_dev;      // the same memory as the device addresses it
   int nb[2];             // blocks of the check in each slot
-  hipEvent_t ev[2];      // completion of each slot's copy
+  hipEvent_t ev[2];      // completion of each slot's partial sums
   double* admm_change;   // host, nullable: outer x (iters - 1) measured changes
   double* warp_change;   // host, nullable: outer - 1 measured changes
   int32_t* iters_run;    // host, nullable: ADMM iterations of each warping
   int outer_run;
 };
+
 // Enqueue the partial sums of |a - b|^2 and |a|^2 over n floats, written by
 // the kernel into read-back slot `slot`.
 nadmm_status change_enqueue(const float* a, const float* b, size_t n, StopRule* stop, int slot,
