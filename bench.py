@@ -155,9 +155,10 @@ def log(msg):
 
 
 def cpu_baseline(pair, w, extra=None):
-    """The FP64 oracle on a bounded sample: one warping (warp, gradient,
-    `iters` ADMM iterations, composition) of the same workload, scaled to
-    registrations/s (a registration is `outer` such warpings)."""
+    """The FP64 oracle on a bounded sample: the first half of the
+    registration's warpings (each: warp of the moving image by the current
+    displacement, gradient, `iters` ADMM iterations, composition) of the same
+    workload, scaled to registrations/s."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -166,16 +167,18 @@ def cpu_baseline(pair, w, extra=None):
     fixed = pair.fixed.astype(np.float64)
     moving = pair.moving.astype(np.float64)
     u = np.zeros((3,) + fixed.shape)
+    n_w = max(1, w["outer"] // 2)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        _, J, r = O.warp_grad_residual(moving, fixed, u)
-        res = O.admm(J, r, w["lam"], w["theta"], w["order"], w["iters"])
-        O.compose(u, res.w)
+        for _ in range(n_w):
+            _, J, r = O.warp_grad_residual(moving, fixed, u)
+            res = O.admm(J, r, w["lam"], w["theta"], w["order"], w["iters"])
+            u = O.compose(u, res.w)
         dt = time.perf_counter() - t0
-    out = {"value": 1.0 / (w["outer"] * dt), "unit": "registrations/s", "cores": 1, "kind": "oracle",
-           "sample": f"one warping ({w['iters']} ADMM iterations + warp + compose) of {w['outer']}, "
+    out = {"value": n_w / (w["outer"] * dt), "unit": "registrations/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n_w} of the {w['outer']} warpings ({w['iters']} ADMM iterations + warp + compose each), "
                      f"numpy float64 single thread, {dt:.2f} s"}
-    out["s_per_admm_iter"] = round(dt / w["iters"], 4)
+    out["s_per_admm_iter"] = round(dt / (n_w * w["iters"]), 4)
     out["others"] = cpu_others(extra or {})
     return out
 
