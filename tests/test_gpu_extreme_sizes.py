@@ -99,3 +99,20 @@ def test_smallest_grid(api):
     e = O.register(f64(f), f64(m), lam, theta, order, 3, 5)
     assert np.abs(host(reg["disp"]) - e.disp).max() < 1e-3
     assert np.abs(host(reg["warped"]) - e.warped).max() < 1e-4
+
+
+def test_largest_grid_threshold_checks(api):
+    """256^3 with the threshold checks running but unreachable (tolerance 0:
+    no iterate repeats exactly) and switched off: both equal the fixed-count
+    registration bit for bit, and every measured change is a finite
+    positive number."""
+    d = (256, 256, 256)
+    f = gpu(synth.random_volume(d, seed=98, smooth_kmax=4))
+    m = gpu(synth.random_volume(d, seed=99, smooth_kmax=4))
+    ref = api.register(f, m, 0.01, 0.1, 2, 2, 4)
+    on = api.register_threshold(f, m, 0.01, 0.1, 2, 2, 4, 0.0, 0.0)
+    assert on["iters_run"] == [4, 4] and on["outer_run"] == 2
+    assert all(0 < x < float("inf") for c in on["admm_change"] for x in c) and len(on["admm_change"][0]) == 2
+    assert torch.equal(on["disp"], ref["disp"]) and torch.equal(on["warped"], ref["warped"])
+    off = api.register_threshold(f, m, 0.01, 0.1, 2, 2, 4, -1.0, -1.0)
+    assert torch.equal(off["disp"], ref["disp"])
