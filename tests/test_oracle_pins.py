@@ -99,6 +99,76 @@ def test_p1_nesterov_scalars():
     assert np.all(np.diff(g) > 0) and g[-1] < 1.0
 
 
+# The first extrapolation weights of Eq. (5), gamma_k = (alpha^k - 1) / alpha^{k+1}
+# with alpha^0 = 1, typed in to ten digits (evaluated once from the printed
+# recurrence, independently of the oracle).
+TYPED_GAMMAS = (0.0, 0.2817535251, 0.4340427828, 0.5310638054)
+
+
+def dense_admm_schedule(J, r, lam, theta, order, gammas):
+    """Eq. (5) written out with dense operators on a tiny grid, iteration by
+    iteration in the paper's order, with the extrapolation weight of each step
+    taken from ``gammas``: iteration k uses w_hat^k = w^{k-1} +
+    gammas[k-1] (w^{k-1} - w^{k-2}) (likewise b_hat), w^{-1} = b^{-1} = 0 and
+    w_hat^0 = b_hat^0 = 0.  The v-step is a dense 3x3 solve per voxel, the
+    w-step a dense solve of (lambda L^n + theta I) w = theta (v + b_hat)."""
+    d = (J.shape[3], J.shape[2], J.shape[1])
+    V = J[0].size
+    A = lam * np.linalg.matrix_power(dense_neg_laplacian(d), order) + theta * np.eye(V)
+    Jf = J.reshape(3, V)
+    rf = r.reshape(V)
+    zero = np.zeros((3, V))
+    w_hat, b_hat, w_prev, b_prev = zero, zero, zero, zero
+    out = []
+    for k in range(len(gammas) + 1):
+        a = w_hat - b_hat
+        v = np.empty((3, V))
+        for i in range(V):
+            M = np.outer(Jf[:, i], Jf[:, i]) + theta * np.eye(3)
+            v[:, i] = np.linalg.solve(M, theta * a[:, i] - Jf[:, i] * rf[i])
+        w = np.stack([np.linalg.solve(A, theta * (v[c] + b_hat[c])) for c in range(3)])
+        b = b_hat + v - w
+        out.append((v.reshape(J.shape), w.reshape(J.shape), b.reshape(J.shape)))
+        if k < len(gammas):
+            g = gammas[k]
+            w_hat = w + g * (w - w_prev)
+            b_hat = b + g * (b - b_prev)
+            w_prev, b_prev = w, b
+    return out
+
+
+def test_p1b_extrapolation_schedule_against_dense_recurrence():
+    """Iterates v^k, w^k, b^k for k = 0..4 of the oracle's ADMM equal the dense
+    evaluation of Eq. (5) with the typed-in gamma_0..gamma_3 (gamma_1 first
+    enters at iteration 2).  The same dense recurrence with the weights
+    shifted by one index (iteration k extrapolating with gamma_k) is a
+    different trajectory, so an index mistake in the oracle fails here."""
+    rng = np.random.default_rng(22)
+    J = rng.uniform(0.1, 0.4, size=(3, 4, 4, 4)) * rng.choice([-1, 1], size=(3, 4, 4, 4))
+    r = rng.uniform(-0.5, 0.5, size=(4, 4, 4))
+    lam, theta, order = 0.5, 0.1, 2
+    res = O.admm(J, r, lam, theta, order, 5, history=True)
+    assert np.allclose(res.gammas[:4], TYPED_GAMMAS, rtol=0, atol=1e-10)
+    ref = dense_admm_schedule(J, r, lam, theta, order, TYPED_GAMMAS)
+    for k, (v, w, b) in enumerate(ref):
+        h = res.history[k]
+        for name, got, want in (("v", h["v"], v), ("w", h["w"], w), ("b", h["b"], b)):
+            err = np.abs(got - want).max() / np.abs(want).max()
+            assert err < 1e-9, (k, name, err)
+    # discriminating power: the schedule shifted by one index (gamma_k at
+    # iteration k) already differs at iteration 1, and by far more than the
+    # tolerance above from iteration 2 on
+    shifted = dense_admm_schedule(J, r, lam, theta, order, TYPED_GAMMAS[1:] + (0.5987785941,))
+    for k in (1, 2, 3, 4):
+        err = np.abs(shifted[k][1] - ref[k][1]).max() / np.abs(ref[k][1]).max()
+        assert err > 1e-3, (k, err)
+    # and so does the schedule without momentum (every gamma zero)
+    plain = dense_admm_schedule(J, r, lam, theta, order, (0.0, 0.0, 0.0, 0.0))
+    assert np.abs(plain[1][1] - ref[1][1]).max() == 0.0  # gamma_0 = 0: iterations 0, 1 agree
+    for k in (2, 3, 4):
+        assert np.abs(plain[k][1] - ref[k][1]).max() / np.abs(ref[k][1]).max() > 1e-3, k
+
+
 # ---------------------------------------------------------------------------
 # P2  Laplacian symbol (Sec. 3, text after Eq. (6))
 # ---------------------------------------------------------------------------
