@@ -83,6 +83,12 @@ typedef struct {
 /* NADMM_ABI_VERSION of the loaded library. */
 int nadmm_abi_version(void);
 
+/* Hex SHA-256 (64 characters, static string) of the sources this library
+ * was compiled from: the names and contents of the HIP sources and headers
+ * of the package's csrc/ directory and of this header, in name order.  A
+ * caller can compare it with the sources on disk to detect a stale build. */
+const char* nadmm_source_digest(void);
+
 /* Human-readable name of a status code (static string). */
 const char* nadmm_status_string(nadmm_status s);
 

@@ -41,6 +41,7 @@ class NadmmError(RuntimeError):
 _P = ctypes.c_void_p
 _SIGS = {
     "nadmm_abi_version": ([], ctypes.c_int),
+    "nadmm_source_digest": ([], ctypes.c_char_p),
     "nadmm_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "nadmm_last_error": ([], ctypes.c_char_p),
     "nadmm_workspace_size": ([Dims, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -96,6 +97,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = res
+    if path == LIB_PATH:
+        from .build import sources_digest
+        built, now = lib.nadmm_source_digest().decode(), sources_digest()
+        if built != now:
+            raise RuntimeError(f"{path} was built from other sources (digest {built[:12]}, sources "
+                               f"{now[:12]}): rebuild it with `python -m paper_2109_12688_amd.build`")
     _lib = lib
     return lib
 

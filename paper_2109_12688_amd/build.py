@@ -4,6 +4,7 @@ Usage:  python -m paper_2109_12688_amd.build      (or build() from Python)
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -27,6 +28,25 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_files() -> list:
+    """Every file the library is compiled from: the HIP sources and headers
+    of csrc/ and the public header."""
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                   if f.endswith((".hip", ".h")))
+    return files + [os.path.join(ROOT, "include", "nadmm.h")]
+
+
+def sources_digest() -> str:
+    """SHA-256 over the names and contents of source_files(); compiled into
+    the library (nadmm_source_digest) so that a stale build is detected."""
+    h = hashlib.sha256()
+    for path in source_files():
+        h.update(os.path.basename(path).encode() + b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -37,7 +57,8 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP source into libnadmm.so (always rebuilds)."""
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
+    cmd = [hipcc(), *HIPCC_FLAGS, f'-DNADMM_SOURCE_DIGEST="{sources_digest()}"',
+           "-I", os.path.join(ROOT, "include"),
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

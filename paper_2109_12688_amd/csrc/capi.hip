@@ -571,7 +571,12 @@ nadmm_status check_pyramid(const nadmm_dims& d, const nadmm_pyramid* pyr) {
 
 extern "C" {
 
+#ifndef NADMM_SOURCE_DIGEST
+#define NADMM_SOURCE_DIGEST "unknown"
+#endif
 int nadmm_abi_version(void) { return NADMM_ABI_VERSION; }
+
+const char* nadmm_source_digest(void) { return NADMM_SOURCE_DIGEST; }
 
 const char* nadmm_status_string(nadmm_status s) {
   switch (s) {
@@ -624,8 +629,8 @@ nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, doubl
   stop.admm_change = admm_change;
   stop.warp_change = warp_change;
   stop.iters_run = iters_run;
-  const int cells = p->outer * (p->iters - 1);
-  for (int i = 0; admm_change && i < cells; ++i) admm_change[i] = NAN;
+  const int64_t cells = (int64_t)p->outer * (p->iters - 1);  // up to ~1e10: 64-bit
+  for (int64_t i = 0; admm_change && i < cells; ++i) admm_change[i] = NAN;
   for (int i = 0; warp_change && i + 1 < p->outer; ++i) warp_change[i] = NAN;
   for (int i = 0; iters_run && i < p->outer; ++i) iters_run[i] = 0;
   CHECK(register_impl(d, p, fixed, moving, nullptr, disp, warped, nullptr, workspace, workspace_bytes,

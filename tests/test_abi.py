@@ -38,6 +38,15 @@ def test_header_functions_are_exported(lib):
     assert set(names) == set(_lib.EXPORTS)
 
 
+def test_library_built_from_these_sources(lib):
+    """The digest compiled into the loaded library is the digest of the
+    sources on disk (load() refuses a stale build)."""
+    from paper_2109_12688_amd.build import source_files, sources_digest
+    assert lib.nadmm_source_digest().decode() == sources_digest()
+    names = [os.path.basename(f) for f in source_files()]
+    assert "capi.hip" in names and "kernels.hip" in names and names[-1] == "nadmm.h"
+
+
 def test_abi_version_and_status_strings(lib):
     assert lib.nadmm_abi_version() == 1
     for code, name in _lib.STATUS_NAMES.items():

@@ -105,14 +105,16 @@ def test_largest_grid_threshold_checks(api):
     """256^3 with the threshold checks running but unreachable (tolerance 0:
     no iterate repeats exactly) and switched off: both equal the fixed-count
     registration bit for bit, and every measured change is a finite
-    positive number."""
+    positive number.  Three warpings, so that the warping check runs too
+    (after the second warping; the last one ends the loop anyway)."""
     d = (256, 256, 256)
     f = gpu(synth.random_volume(d, seed=98, smooth_kmax=4))
     m = gpu(synth.random_volume(d, seed=99, smooth_kmax=4))
-    ref = api.register(f, m, 0.01, 0.1, 2, 2, 4)
-    on = api.register_threshold(f, m, 0.01, 0.1, 2, 2, 4, 0.0, 0.0)
-    assert on["iters_run"] == [4, 4] and on["outer_run"] == 2
+    ref = api.register(f, m, 0.01, 0.1, 2, 3, 4)
+    on = api.register_threshold(f, m, 0.01, 0.1, 2, 3, 4, 0.0, 0.0)
+    assert on["iters_run"] == [4, 4, 4] and on["outer_run"] == 3
     assert all(0 < x < float("inf") for c in on["admm_change"] for x in c) and len(on["admm_change"][0]) == 2
+    assert len(on["warp_change"]) == 1 and 0 < on["warp_change"][0] < float("inf")
     assert torch.equal(on["disp"], ref["disp"]) and torch.equal(on["warped"], ref["warped"])
-    off = api.register_threshold(f, m, 0.01, 0.1, 2, 2, 4, -1.0, -1.0)
+    off = api.register_threshold(f, m, 0.01, 0.1, 2, 3, 4, -1.0, -1.0)
     assert torch.equal(off["disp"], ref["disp"])
