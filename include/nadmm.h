@@ -310,6 +310,21 @@ nadmm_status nadmm_jacobian(nadmm_dims d, const float* disp, float* det, double*
                             int64_t* n_nonpos, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* nadmm_jacobian without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops that must not call
+ * hipMalloc).  Same arguments, results and errors as nadmm_jacobian, bit for
+ * bit; the partial sums of the reduction live in a 32 KB array of device
+ * memory inside the library (one per GPU, allocated when the library's code
+ * is loaded on that GPU and held until the process ends), so the call
+ * allocates nothing.  Every supported size fits that array (the reduction
+ * uses at most 1024 blocks); a size that did not would be rejected with
+ * NADMM_ERR_UNSUPPORTED_SIZE before anything is enqueued.  All calls on one
+ * GPU share the array: calls whose work overlaps in time on the same GPU
+ * (different streams or threads without ordering between them) race and
+ * give undefined results.  The stream must belong to the current device. */
+nadmm_status nadmm_jacobian_noalloc(nadmm_dims d, const float* disp, float* det, double* stats,
+                                    int64_t* n_nonpos, void* stream);
+
 /* Output check (not an operation of the paper): the number of NaN or
  * infinite values among `count` volumes stored back to back at `field`
  * (count = 3 for a displacement or velocity field, 1 for an image), written

@@ -73,6 +73,7 @@ _SIGS = {
     "nadmm_compose": ([Dims, _P, _P, _P, _P], ctypes.c_int),
     "nadmm_expmap": ([Dims, _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_jacobian": ([Dims, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "nadmm_jacobian_noalloc": ([Dims, _P, _P, _P, _P, _P], ctypes.c_int),
     "nadmm_count_nonfinite": ([Dims, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
     "nadmm_profile_enable": ([ctypes.c_int], ctypes.c_int),
     "nadmm_profile_replay": ([Dims, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t,

@@ -368,6 +368,19 @@ def jacobian(disp: torch.Tensor, want_det: bool = False, ws: torch.Tensor | None
     return stats, nneg, det
 
 
+def jacobian_noalloc(disp: torch.Tensor, want_det: bool = False):
+    """jacobian() through nadmm_jacobian_noalloc: no workspace, the
+    reduction's partials in the library's own device array."""
+    _check(disp, "disp")
+    shp = tuple(disp.shape[1:])
+    det = torch.empty(shp, dtype=torch.float32, device=disp.device) if want_det else None
+    stats = torch.empty(3, dtype=torch.float64, device=disp.device)
+    nneg = torch.empty(1, dtype=torch.int64, device=disp.device)
+    _lib.call("nadmm_jacobian_noalloc", dims_of(shp), _ptr(disp), _ptr(det), _ptr(stats), _ptr(nneg),
+              _stream())
+    return stats, nneg, det
+
+
 def count_nonfinite(field: torch.Tensor) -> torch.Tensor:
     """Device int64 [1]: number of NaN or infinite entries of a scalar volume
     (nz, ny, nx) or of stacked volumes (C, nz, ny, nx)."""

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnadmm.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "reduce.hip", "capi.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "reduce.hip", "capi.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -16,6 +16,12 @@
 #include "kernels.h"
 #include "reduce.h"
 
+namespace nadmm {
+// Sets the calling thread's nadmm_last_error() message and returns s
+// (defined in capi.hip, where that message lives).
+nadmm_status set_last_error(nadmm_status s, const char* msg);
+}  // namespace nadmm
+
 using namespace nadmm;
 
 namespace {
@@ -29,6 +35,15 @@ nadmm_status fail(nadmm_status s, const char* fmt, ...) {
   va_end(ap);
   return s;
 }
+
+}  // namespace
+
+nadmm_status nadmm::set_last_error(nadmm_status s, const char* msg) {
+  snprintf(g_err, sizeof(g_err), "%s", msg);
+  return s;
+}
+
+namespace {
 
 #define HIP_TRY(expr)                                                                    \
   do {                                                                                   \

@@ -167,6 +167,9 @@ hipError_t launch_grad_transpose(const Geo& g, const float* gJ, const float* gr,
 size_t dot_partials();
 hipError_t launch_dot(size_t n, const float* a, const float* b, double scale, bool accumulate,
                       double* partial, double* out, hipStream_t st);
+// Blocks of the first Jacobian launch; `partial` holds 4 doubles per block
+// (min, max, sum, count of det <= 0), every one written before it is read.
+int jacobian_blocks(const Geo& g);
 hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* partial,
                            double* stats, int64_t* n_nonpos, hipStream_t st);
 

@@ -1589,10 +1589,14 @@ __global__ void k_jac_final(int nparts, int V, const JacAcc* __restrict__ partia
   }
 }
 
+int jacobian_blocks(const Geo& g) {
+  const int nb = (g.V + 255) / 256;
+  return nb > kJacBlocks ? kJacBlocks : nb;
+}
+
 hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* partial,
                            double* stats, int64_t* n_nonpos, hipStream_t st) {
-  int nb = (g.V + 255) / 256;
-  if (nb > kJacBlocks) nb = kJacBlocks;
+  const int nb = jacobian_blocks(g);
   JacAcc* part = reinterpret_cast<JacAcc*>(partial);
   hipLaunchKernelGGL(k_jac_partial, dim3(nb), dim3(256), 0, st, g, disp, det, part);
   hipError_t e = hipGetLastError();
