@@ -31,7 +31,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, packed (two lanes per instruction)
+# Without packed FP32 instructions (disabled for every kernel here) one wave64
+# FP32 FMA takes 4 cycles on a SIMD: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+FP32_NONPACKED_PEAK_TFLOPS = 78.6
+# Compulsory bytes of one ADMM iteration (read w, w_old, b, b_old, J, r; write
+# w, b: 22 float32 values per voxel), the unit the iteration rate is priced in.
+ITER_FLOOR_BYTES_PER_VOXEL = 88.0
 KERNEL_SOURCES = ["kernels.hip", "kernels.h", "fft_lds.h", "pointwise.h"]
 # rocprofv3 kernel-name prefixes of the replayable kernels
 KERNEL_NAMES = {"pass_a_fwd_x": "nadmm::k_pass_a<", "pass_b_yz_solve": "nadmm::k_pass_b<",
@@ -438,24 +444,50 @@ def grad_time(api, torch, synth, pair, reps=5):
             "ms_per_forward_warping": round(t_fwd, 3), "gradient_vs_forward": round(t_grad / t_fwd, 3)}
 
 
-def bf16_vs_plain(api, torch, synth, pair, reps=3):
-    """The precision workload (192x192x128 phantom, n = 3, lambda = 0.005,
-    10 x 30) registered from bfloat16 and from float32 images on the same
-    GPU; ms per registration of each (event-timed, inputs resident)."""
-    name = "phantom192x192x128"
-    w = synth.WORKLOADS[name]
+def sample_errors(res, golden, key):
+    """Per-output errors of one registration against the FP64 oracle's
+    stored samples (tests/golden/, written by make_golden.py from the oracle
+    only): displacement (max over components), warped intensity, and both
+    restricted to the samples whose oracle determinant stays above 0.1 in the
+    9^3 neighbourhood (away from folds)."""
+    import numpy as np
+    idx = np.array(golden["indices"])
+    g = golden[key]
+    disp = res["disp"].reshape(3, -1)[:, idx].double().cpu().numpy()
+    warped = res["warped"].reshape(-1)[idx].double().cpu().numpy()
+    de = np.abs(disp - np.array(g["disp"])).max(axis=0)
+    we = np.abs(warped - np.array(g["warped"]))
+    away = np.array(golden["nbhd_min_det"][key]) > 0.1
+    return {"samples": int(len(idx)), "disp_err_max": float(de.max()), "disp_err_mean": float(de.mean()),
+            "warped_err_max": float(we.max()), "warped_err_mean": float(we.mean()),
+            "samples_beyond_1e-3_voxel_or_1e-4_intensity": int(((de > 1e-3) | (we > 1e-4)).sum()),
+            "samples_away_from_folds": int(away.sum()),
+            "disp_err_max_away_from_folds": float(de[away].max()),
+            "warped_err_max_away_from_folds": float(we[away].max()),
+            "oracle_min_det_J": g["jacobian"]["min"], "oracle_n_det_nonpos": g["jacobian"]["n_nonpos"]}
+
+
+def dram_check(api, torch, pair, w, single_iter_ms, reps=3, copies=8):
+    """The headline iteration with a working set far beyond the 256 MB
+    Infinity Cache: `copies` copies of the same pair in one batched call
+    (one launch per phase covers all of them), the ADMM iteration time per
+    pair from the difference of two iteration counts as for the headline
+    figure.  About 70 MB per pair per iteration, 560 MB for 8 pairs: what
+    this rate loses against the single pair's is what the Infinity Cache
+    was adding."""
+    import numpy as np
     shp = pair.fixed.shape
-    ws = api.workspace(shp)
-    f32 = (torch.from_numpy(pair.fixed).cuda(), torch.from_numpy(pair.moving).cuda())
-    b16 = tuple(t.to(torch.bfloat16) for t in f32)
-    out = {"disp": torch.empty((3,) + shp, device="cuda"), "warped": torch.empty(shp, device="cuda")}
+    f = torch.from_numpy(np.stack([pair.fixed] * copies)).cuda()
+    m = torch.from_numpy(np.stack([pair.moving] * copies)).cuda()
+    ws = api.workspace_batch(shp, copies)
+    out = None
     stream = torch.cuda.current_stream()
 
-    def ms(imgs):
-        def run():
-            api.register(imgs[0], imgs[1], w["lam"], w["theta"], w["order"], w["outer"], w["iters"],
-                         ws=ws, out=out)
-        run()
+    def ms(iters):
+        nonlocal out
+        run = lambda: api.register_batch(f, m, w["lam"], w["theta"], w["order"], w["outer"], iters, ws=ws,
+                                          out=out)
+        out = run()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -465,17 +497,119 @@ def bf16_vs_plain(api, torch, synth, pair, reps=3):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    plain, bf = ms(f32), ms(b16)
+    half = w["iters"] // 2
+    t_full, t_half = ms(w["iters"]), ms(half)
+    it_ms = (t_full - t_half) / (w["outer"] * (w["iters"] - half) * copies)
+    V = int(np.prod(shp))
+    ach = ITER_FLOOR_BYTES_PER_VOXEL * V / (it_ms * 1e-3) / 1e9
+    log(f"{copies} copies batched: {t_full / copies:.3f} ms per pair, {1e3 * it_ms:.2f} us per pair-iteration")
+    nz, ny, nx = shp
+    per_pair = 32 * V + 24 * (nx // 2 + 1) * ny * nz  # s^k, s^(k-1), I1^w, r and the half spectrum
+    return {"pairs": copies, "working_set_mb_per_iteration": round(copies * per_pair / 1e6, 1),
+            "ms_per_registration_per_pair": round(t_full / copies, 4),
+            "ms_per_admm_iter_per_pair": round(it_ms, 5),
+            "iteration_achieved_gbs": round(ach, 1), "iteration_frac": round(ach / HBM_PEAK_GBS, 4),
+            "vs_single_pair_iteration": round(single_iter_ms / it_ms, 4)}
+
+
+def bf16_vs_plain(api, torch, synth, pair, reps=3):
+    """The precision workload (192x192x128 phantom, n = 3, lambda = 0.005,
+    10 x 30) registered from bfloat16 and from float32 images on the same
+    GPU: ms per registration of each (event-timed, inputs resident), each
+    output's error against the FP64 oracle's stored samples, and the ADMM
+    iteration's roofline at this size (a working set larger than the
+    256 MB Infinity Cache)."""
+    name = "phantom192x192x128"
+    w = synth.WORKLOADS[name]
+    shp = pair.fixed.shape
+    ws = api.workspace(shp)
+    f32 = (torch.from_numpy(pair.fixed).cuda(), torch.from_numpy(pair.moving).cuda())
+    b16 = tuple(t.to(torch.bfloat16) for t in f32)
+    out = {"disp": torch.empty((3,) + shp, device="cuda"), "warped": torch.empty(shp, device="cuda")}
+    stream = torch.cuda.current_stream()
+
+    def run(imgs):
+        return api.register(imgs[0], imgs[1], w["lam"], w["theta"], w["order"], w["outer"], w["iters"],
+                            ws=ws, out=out)
+
+    def ms(imgs):
+        run(imgs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run(imgs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    with open(os.path.join(ROOT, "tests", "golden", f"{name}_oracle_samples.json")) as f:
+        golden = json.load(f)
+    plain = ms(f32)
+    torch.cuda.synchronize()
+    err_fp32 = sample_errors(out, golden, "fp32")
+    bf = ms(b16)
+    torch.cuda.synchronize()
+    err_bf16 = sample_errors(out, golden, "bf16")
     stats, nneg, _ = api.jacobian(out["disp"], ws=ws)
     torch.cuda.synchronize()
+    err_bf16.update({"min_det_J": float(stats[0].item()), "n_det_nonpos": int(nneg.item())})
+    run(f32)
+    stats, nneg, _ = api.jacobian(out["disp"], ws=ws)
+    torch.cuda.synchronize()
+    err_fp32.update({"min_det_J": float(stats[0].item()), "n_det_nonpos": int(nneg.item())})
     log(f"{name}: float32 images {plain:.3f} ms, bfloat16 images {bf:.3f} ms per registration")
+    log(f"{name}: errors vs oracle samples, float32 images {err_fp32}, bfloat16 images {err_bf16}")
+    rl = iteration_rooflines(api, lambda: run(f32), shp, w, ws, name, reps=50)
     return {"workload": name, "dims_xyz": list(w["dims"]), "outer": w["outer"], "iters": w["iters"],
             "order": w["order"], "lambda": w["lam"], "steps": reps,
             "ms_per_registration_fp32_images": round(plain, 3),
             "ms_per_registration_bf16_images": round(bf, 3),
             "registrations_per_s_bf16": round(1000.0 / bf, 3),
             "bf16_vs_plain": round(plain / bf, 4),
-            "min_det_J_bf16": float(stats[0].item()), "n_det_nonpos_bf16": int(nneg.item())}
+            "errors_vs_oracle": {"fp32_images": err_fp32, "bf16_images": err_bf16},
+            "rooflines": rl}
+
+
+def iteration_rooflines(api, step, shp, w, ws, workload, reps=200):
+    """Rooflines of the ADMM iteration, measured by replaying its kernels on
+    the state a registration left in the workspace (nadmm_profile_replay:
+    `reps` launches back to back between two HIP events on the launch
+    stream, so launch gaps are included).
+
+    admm_iteration: the unit of the iteration rate, priced at its compulsory
+    88 B/voxel against the HBM peak (the two launches move 92 B/voxel).
+    pass_ca_iter: the fused x-line pass, HBM-bound, at its own 68 B/voxel.
+    pass_b_yz_solve: the y-z spectral pass at its 24 B/voxel against HBM, and
+    its nominal FFT work against the non-packed FP32 vector rate."""
+    import numpy as np
+    V = int(np.prod(shp))
+    out = {}
+    for kind in ("admm_iteration", "pass_ca_iter", "pass_b_yz_solve"):
+        step()
+        avg_s = api.profile_replay(shp, kind, reps, w["lam"], w["theta"], w["order"], ws) / 1e3
+        if kind == "admm_iteration":
+            bpl = ITER_FLOOR_BYTES_PER_VOXEL * V
+            tr = [stored_traffic(workload, k) for k in ("pass_ca_iter", "pass_b_yz_solve")]
+            traffic = (sum(t["traffic_bytes_per_launch"] for t in tr) if all(tr) else None)
+        else:
+            bpl = BYTES_PER_VOXEL[kind] * V
+            t = stored_traffic(workload, kind)
+            traffic = t["traffic_bytes_per_launch"] if t else None
+        ach = bpl / avg_s / 1e9
+        r = {"kernel": kind, "avg_us": round(avg_s * 1e6, 3), "bytes_per_launch": bpl, "bound": "hbm",
+             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
+        if kind == "admm_iteration":
+            r["kernel"] = "admm_iteration (pass_ca_iter + pass_b_yz_solve)"
+            r["bytes_per_voxel"] = ITER_FLOOR_BYTES_PER_VOXEL
+        if kind == "pass_b_yz_solve":
+            fl = pass_b_flops(w["dims"])
+            r["alu"] = {"achieved": round(fl / avg_s / 1e12, 2), "peak": FP32_NONPACKED_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(fl / avg_s / 1e12 / FP32_NONPACKED_PEAK_TFLOPS, 4),
+                        "flops_per_launch": round(fl)}
+        out[kind] = r
+    return out
 
 
 def main():
@@ -551,7 +685,32 @@ def main():
     per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     log(f"{ms_per_step:.3f} ms/registration (wall {1e3 * wall / args.steps:.3f})")
 
+    # ms per ADMM iteration as the inner-loop time over outer x iters: the
+    # same registration at `iters` and at iters / 2 iterations per warping
+    # differ by exactly outer x (iters - iters / 2) iterations (a warping's
+    # first iteration, its composition and the warp are in both)
+    half = w["iters"] // 2
+
+    def reg_ms(iters, reps):
+        run = lambda: api.register(fixed, moving, w["lam"], w["theta"], w["order"], w["outer"], iters,
+                                   ws=ws, out=out)
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_full, t_half = reg_ms(w["iters"], args.steps), reg_ms(half, args.steps)
+    ms_per_iter = (t_full - t_half) / (w["outer"] * (w["iters"] - half))
+    log(f"ms per ADMM iteration: ({t_full:.3f} - {t_half:.3f}) / ({w['outer']} x {w['iters'] - half})"
+        f" = {ms_per_iter:.5f}")
+
     # per-kernel durations from HIP events bracketing each library launch
+    # (each bracket adds the launch gap)
     _lib.profile_enable(True)
     for _ in range(args.profile_steps):
         step()
@@ -560,44 +719,11 @@ def main():
     _lib.profile_enable(False)
     kernels = {}
     for k, (n, ms) in prof.items():
-        kernels[k] = {"launches_per_step": n / args.profile_steps, "avg_us": 1e3 * ms / n}
-    # one ADMM iteration = the fused pass C + A and one pass B
-    per_iter_us = (1e3 * prof["pass_ca_iter"][1] / prof["pass_ca_iter"][0] +
-                   1e3 * prof["pass_b_yz_solve"][1] / prof["pass_b_yz_solve"][0])
-    # Both iteration kernels: duration re-measured by replaying each 200 times
-    # back to back between two HIP events on its stream (per-launch event
-    # brackets add launch gaps).  The fused x-line pass is bound by HBM; the
-    # y-z pass (one plane per CU) by the VALU issue of the CUs holding its
-    # planes, so its roofline is the FP32 vector rate of its nominal FFT work.
-    # `roofline` is the one with the larger share of the step.
-    rooflines = {}
-    for kind in ("pass_ca_iter", "pass_b_yz_solve"):
-        if kind not in prof:
-            continue
-        step()
-        avg_s = api.profile_replay(shp, kind, 200, w["lam"], w["theta"], w["order"], ws) / 1e3
-        trec = stored_traffic(args.workload, kind)
-        bpl = BYTES_PER_VOXEL[kind] * V
-        r = {"kernel": kind, "avg_us": round(avg_s * 1e6, 3),
-             "avg_us_event_bracketed": round(1e3 * prof[kind][1] / prof[kind][0], 3),
-             "bytes_per_launch": bpl,
-             "traffic": trec["traffic_bytes_per_launch"] if trec else None,
-             "traffic_read_write": ([trec["read_bytes_per_launch"], trec["write_bytes_per_launch"]]
-                                    if trec else None)}
-        if kind == "pass_b_yz_solve":
-            fl = pass_b_flops(w["dims"])
-            ach = fl / avg_s / 1e12
-            r.update({"bound": "alu", "achieved": round(ach, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                      "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
-                      "flops_per_launch": round(fl), "hbm_gbs": round(bpl / avg_s / 1e9, 1)})
-        else:
-            ach = bpl / avg_s / 1e9
-            r.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": round(ach / HBM_PEAK_GBS, 4)})
-        rooflines[kind] = r
-    dom = max(rooflines, key=lambda k: prof[k][1])
-    roofline = dict(rooflines[dom])
+        kernels[k] = {"launches_per_step": n / args.profile_steps, "avg_us_event_bracketed": 1e3 * ms / n}
+    rooflines = iteration_rooflines(api, step, shp, w, ws, args.workload)
+    roofline = dict(rooflines["admm_iteration"])
     roofline["copy_gbs"] = round(copy_gbs, 1)
+    roofline["ms_per_admm_iter_differenced"] = round(ms_per_iter, 5)
 
     stats, nneg, _ = api.jacobian(out["disp"], ws=ws)
     torch.cuda.synchronize()
@@ -610,7 +736,9 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
         "ms_per_step_p10_p50_p90": [round(float(np.percentile(per_step, q)), 4) for q in (10, 50, 90)],
-        "ms_per_admm_iter": round(per_iter_us / 1e3, 5),
+        "ms_per_admm_iter": round(ms_per_iter, 5),
+        "ms_per_admm_iter_method": (f"(registration at {w['iters']} iterations per warping - at {half}) / "
+                                    f"({w['outer']} warpings x {w['iters'] - half})"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -625,6 +753,7 @@ def main():
         "min_det_J": float(stats[0].item()),
         "n_det_nonpos": int(nneg.item()),
     }
+    res["dram_check"] = dram_check(api, torch, pair, w, ms_per_iter)
     if not args.no_bf16:
         res["bf16"] = bf16_vs_plain(api, torch, synth, inputs["bf16"])
     if not args.no_grad:

@@ -352,8 +352,9 @@ int nadmm_profile_read(int max, const char** names, int64_t* counts, double* tot
  * warping's first solve, 1 = y-z spectral pass, 2 = the fused x pass of the
  * iteration loop (inverse x transform, data step and new state, extrapolation
  * and forward x transform of the next solve's input; replayed with zero
- * extrapolation weights so that the state stays bounded).  The replayed
- * launches overwrite the workspace's iteration state. */
+ * extrapolation weights so that the state stays bounded), 3 = one whole ADMM
+ * iteration (kind 2 followed by kind 1; *avg_ms is per iteration).  The
+ * replayed launches overwrite the workspace's iteration state. */
 nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t kind, int32_t reps,
                                   void* workspace, size_t workspace_bytes, void* stream,
                                   double* avg_ms);

@@ -11,7 +11,9 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libnadmm.so")
+# NADMM_LIBRARY selects another build of the same sources (the sanitized
+# build of the host-code checks); it must carry the same source digest.
+LIB_PATH = os.environ.get("NADMM_LIBRARY") or os.path.join(PKG, "libnadmm.so")
 
 NADMM_OK = 0
 STATUS_NAMES = {0: "NADMM_OK", 1: "NADMM_ERR_INVALID_ARG", 2: "NADMM_ERR_UNSUPPORTED_SIZE",

@@ -394,7 +394,7 @@ def count_nonfinite(field: torch.Tensor) -> torch.Tensor:
     return out
 
 
-REPLAY_KINDS = {"pass_a_fwd_x": 0, "pass_b_yz_solve": 1, "pass_ca_iter": 2}
+REPLAY_KINDS = {"pass_a_fwd_x": 0, "pass_b_yz_solve": 1, "pass_ca_iter": 2, "admm_iteration": 3}
 
 
 def profile_replay(vol_shape, kind: str, reps: int, lam: float, theta: float, order: int,

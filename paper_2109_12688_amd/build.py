@@ -54,10 +54,28 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libnadmm.so (always rebuilds)."""
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), *HIPCC_FLAGS, f'-DNADMM_SOURCE_DIGEST="{sources_digest()}"',
+# Host-code sanitizers (address, undefined behaviour) for a checking build;
+# the device code is built as usual.
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """Path of the address-sanitizer runtime that a process loading a
+    sanitized build must preload."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "lib", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = shutil.which("clang") or "/opt/rocm/llvm/bin/clang"
+    res = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return res.stdout.strip()
+
+
+def build(verbose: bool = False, out: str = LIB, sanitize: bool = False) -> str:
+    """Compile every HIP source into `out` (libnadmm.so in the package by
+    default; always rebuilds).  sanitize: host code with ASan and UBSan."""
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = [hipcc(), *HIPCC_FLAGS, *(SANITIZE_FLAGS if sanitize else []),
+           f'-DNADMM_SOURCE_DIGEST="{sources_digest()}"',
            "-I", os.path.join(ROOT, "include"),
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
@@ -70,8 +88,8 @@ def build(verbose: bool = False) -> str:
         for line in res.stderr.splitlines():
             if noise not in line:
                 print(line)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -1128,7 +1128,7 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   CHECK(check_params(p, false));
   CHECK(check_ws(d, workspace, workspace_bytes));
   if (!avg_ms) return fail(NADMM_ERR_INVALID_ARG, "avg_ms is NULL");
-  if (kind < 0 || kind > 2) return fail(NADMM_ERR_INVALID_ARG, "kind must be 0, 1 or 2");
+  if (kind < 0 || kind > 3) return fail(NADMM_ERR_INVALID_ARG, "kind must be 0, 1, 2 or 3");
   if (reps < 1 || reps > 10000) return fail(NADMM_ERR_INVALID_ARG, "reps must be in [1, 10000]");
   const Geo g = geo(d);
   const Plans pl = plans(d);
@@ -1157,7 +1157,9 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
   auto launch = [&]() -> hipError_t {
     if (kind == 0) return launch_pass_a(g, pl.x, tb, S1, nullptr, 0.0f, X, st);
     if (kind == 1) return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
-    return launch_pass_c(g, pl.x, tb, kIterFwdIw, a, st);
+    if (kind == 2) return launch_pass_c(g, pl.x, tb, kIterFwdIw, a, st);
+    const hipError_t e = launch_pass_c(g, pl.x, tb, kIterFwdIw, a, st);
+    return e != hipSuccess ? e : launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
