@@ -87,6 +87,8 @@ def parse():
                     help="skip the threshold-stopped registration of the same pair")
     ap.add_argument("--no-pyramid", action="store_true",
                     help="skip the paper's three-level schedule on the same pair")
+    ap.add_argument("--no-dram-check", action="store_true",
+                    help="skip the 8-copy batched registration (the iteration beyond the Infinity Cache)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a device-to-device copy of known size first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -246,9 +248,12 @@ def generate_inputs(args):
 
 
 def batch_vs_plain(api, torch, synth, pairs, reps=2):
-    """The 32 uneven pairs registered one call per pair, and batched: one
-    nadmm_register_batch call per size, the three sizes on separate streams.
-    Wall time of the whole set from HIP events on the launching stream."""
+    """The 32 uneven pairs registered one call per pair; batched per size (one
+    nadmm_register_batch call per size, the three sizes on separate streams,
+    eagerly and replayed from graphs); and in one nadmm_register_mixed call
+    (one launch per phase over every pair of every size, eagerly and replayed
+    from a graph).  Wall time of the whole set from HIP events on the
+    launching stream; every pair checked bit for bit against its own call."""
     import numpy as np
     w = synth.BATCH_PARAMS
     specs = synth.batch_specs(32)
@@ -322,6 +327,25 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
     t_graph = ms(batched_graph)
     same = all(torch.equal(bouts[d]["disp"][j], outs[i]["disp"]) for d, idx in groups.items()
                for j, i in enumerate(idx))  # after the graph replays
+
+    # all 32 pairs in one call, one launch per phase over every size
+    # (nadmm_register_mixed), eagerly and replayed from a graph
+    fl, ml = [f for f, _ in single], [m for _, m in single]
+    wsm = api.workspace_mixed([tuple(f.shape) for f in fl])
+    mixed_out = api.register_mixed(fl, ml, *args, ws=wsm)
+    packed = mixed_out["packed"]
+    t_mixed = ms(lambda: api.register_mixed(fl, ml, *args, ws=wsm, packed=packed))
+    same_mixed = all(torch.equal(mixed_out["disp"][i], outs[i]["disp"]) and
+                     torch.equal(mixed_out["warped"][i], outs[i]["warped"]) for i in range(len(specs)))
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    gm = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gm, stream=gs):
+        api.register_mixed(fl, ml, *args, ws=wsm, packed=packed)
+    torch.cuda.synchronize()
+    t_mixed_graph = ms(lambda: gm.replay())
+    same_mixed = same_mixed and all(torch.equal(mixed_out["disp"][i], outs[i]["disp"]) for i in range(len(specs)))
+    log(f"batch of {len(specs)}: one call over all sizes {t_mixed:.2f} ms, replayed graph {t_mixed_graph:.2f} ms")
     nvox = int(sum(np.prod(d) for d, _ in specs))
     log(f"batch of {len(specs)}: one by one {t_plain:.2f} ms, batched {t_batch:.2f} ms")
     return {"pairs": len(specs), "sizes": {"x".join(map(str, d)): len(idx) for d, idx in groups.items()},
@@ -332,8 +356,12 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
             "pairs_per_s_batched": round(1000.0 * len(specs) / t_batch, 2),
             "batched_vs_one_by_one": round(t_plain / t_batch, 4),
             "batched_graph_vs_one_by_one": round(t_plain / t_graph, 4),
+            "ms_mixed_one_call": round(t_mixed, 3), "ms_mixed_graph": round(t_mixed_graph, 3),
+            "pairs_per_s_mixed": round(1000.0 * len(specs) / t_mixed, 2),
+            "mixed_vs_one_by_one": round(t_plain / t_mixed, 4),
+            "mixed_vs_per_size_streams": round(t_batch / t_mixed, 4),
             "tile_rows": tiles,
-            "bit_identical": bool(same)}
+            "bit_identical": bool(same), "mixed_bit_identical": bool(same_mixed)}
 
 
 # The paper's runtime per pair for the L2 data term with the second-order
@@ -753,7 +781,8 @@ def main():
         "min_det_J": float(stats[0].item()),
         "n_det_nonpos": int(nneg.item()),
     }
-    res["dram_check"] = dram_check(api, torch, pair, w, ms_per_iter)
+    if not args.no_dram_check:
+        res["dram_check"] = dram_check(api, torch, pair, w, ms_per_iter)
     if not args.no_bf16:
         res["bf16"] = bf16_vs_plain(api, torch, synth, inputs["bf16"])
     if not args.no_grad:

@@ -187,6 +187,33 @@ nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_param
                                   const float* init_disp, float* disp, float* warped,
                                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* Registration of pairs of SEVERAL sizes in one call, each launch of the
+ * path (Sec. 2 scheme with the Sec. 3 iteration, as nadmm_register from
+ * u = 0) covering every pair of every size: its workgroups are numbered over
+ * (size class, pair, tile) and each runs the code compiled for its pair's
+ * sizes, so there is one launch per phase for the whole batch.
+ *   npairs     1..4096 pairs; dims (host array of npairs) gives each pair's
+ *              size.  Pairs of one size must be consecutive (at most 8 runs
+ *              of sizes, all different), each size with nx in
+ *              {64, 96, 128, 192} and ny, nz in {32, 64, 96, 128}
+ *              (NADMM_ERR_UNSUPPORTED_SIZE otherwise).
+ *   fixed, moving, warped   scalar volumes of every pair back to back in
+ *              pair order (pair i at offset V_0 + .. + V_{i-1} floats);
+ *              warped may be NULL.
+ *   disp       vector fields of every pair back to back (pair i at
+ *              3 (V_0 + .. + V_{i-1}) floats).
+ *   p          one parameter set for every pair.
+ * Results are those of npairs separate nadmm_register calls, bit for bit
+ * (each pair's arithmetic is the same; the tile autotuner's choice for a
+ * size applies here as well).  Workspace: nadmm_workspace_size_mixed bytes.
+ * Asynchronous; the call enqueues kernel launches only (the batch's
+ * descriptor travels as a kernel argument), so it can be captured in a
+ * graph. */
+nadmm_status nadmm_workspace_size_mixed(int32_t npairs, const nadmm_dims* dims, size_t* bytes);
+nadmm_status nadmm_register_mixed(int32_t npairs, const nadmm_dims* dims, const nadmm_params* p,
+                                  const float* fixed, const float* moving, float* disp, float* warped,
+                                  void* workspace, size_t workspace_bytes, void* stream);
+
 /* Multi-resolution registration (Sec. 4: the three-level pyramid of the
  * first hyper-parameter version caps the ADMM iterations at 10, 5, 5 and the
  * warpings at 10, 10, 5, coarsest level first).  Level l of `levels` (1..4,

@@ -56,6 +56,10 @@ _SIGS = {
     "nadmm_workspace_size_batch": ([Dims, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "nadmm_register_batch": ([Dims, ctypes.c_int32, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P,
                               ctypes.c_size_t, _P], ctypes.c_int),
+    "nadmm_workspace_size_mixed": ([ctypes.c_int32, ctypes.POINTER(Dims), ctypes.POINTER(ctypes.c_size_t)],
+                                   ctypes.c_int),
+    "nadmm_register_mixed": ([ctypes.c_int32, ctypes.POINTER(Dims), ctypes.POINTER(Params), _P, _P, _P, _P, _P,
+                              ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_workspace_size_grad": ([Dims, ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
                                   ctypes.c_int),
     "nadmm_ssd_grad": ([Dims, ctypes.POINTER(Params), ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],

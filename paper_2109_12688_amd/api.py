@@ -9,6 +9,8 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -176,6 +178,73 @@ def register_batch(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta:
               _ptr(moving), _ptr(init_disp), _ptr(disp), _ptr(warped), _ptr(ws),
               ctypes.c_size_t(ws.numel()), _stream())
     return {"disp": disp, "warped": warped}
+
+
+def _dims_array(shapes):
+    arr = (Dims * len(shapes))()
+    for i, shp in enumerate(shapes):
+        arr[i] = dims_of(shp)
+    return arr
+
+
+def workspace_mixed(shapes, device="cuda") -> torch.Tensor:
+    """Workspace of register_mixed for pairs of the given (nz, ny, nx) shapes
+    (any order: the size is that of the grouped order)."""
+    n = ctypes.c_size_t(0)
+    shapes = [tuple(shapes[i]) for i in mixed_order(shapes)]
+    _lib.call("nadmm_workspace_size_mixed", ctypes.c_int32(len(shapes)), _dims_array(shapes), ctypes.byref(n))
+    return torch.empty(int(n.value), dtype=torch.uint8, device=device)
+
+
+def mixed_order(shapes) -> list:
+    """Pair order that puts pairs of one size together (sizes in order of
+    first appearance, pairs of a size in their given order)."""
+    first = {}
+    for i, shp in enumerate(shapes):
+        first.setdefault(tuple(shp), i)
+    return sorted(range(len(shapes)), key=lambda i: (first[tuple(shapes[i])], i))
+
+
+def register_mixed(fixed: list, moving: list, lam: float, theta: float, order: int, outer: int, iters: int,
+                   data_term: int = 2, eps: float = 1e-8, ws: torch.Tensor | None = None,
+                   packed: tuple | None = None) -> dict:
+    """Pairs of several sizes in one call, one launch per phase over all of
+    them (nadmm_register_mixed).  fixed, moving: lists of float32 (nz, ny, nx)
+    tensors in any order (they are grouped by size for the call).  Returns
+    'disp' and 'warped' lists in the given order (views into one buffer
+    each) and 'packed' = (fixed, moving, disp, warped) flat buffers in the
+    grouped order, which a later call may pass back as `packed` to reuse."""
+    shapes = [tuple(f.shape) for f in fixed]
+    if len(moving) != len(fixed):
+        raise ValueError("fixed and moving must have the same number of pairs")
+    for f, m in zip(fixed, moving):
+        _check(f, "fixed")
+        _check(m, "moving", tuple(f.shape))
+    dev = fixed[0].device
+    perm = mixed_order(shapes)
+    gshapes = [shapes[i] for i in perm]
+    sizes = [int(np.prod(shp)) for shp in gshapes]
+    if packed is None:
+        f_flat = torch.cat([fixed[i].reshape(-1) for i in perm])
+        m_flat = torch.cat([moving[i].reshape(-1) for i in perm])
+        d_flat = torch.empty(3 * sum(sizes), dtype=torch.float32, device=dev)
+        w_flat = torch.empty(sum(sizes), dtype=torch.float32, device=dev)
+    else:
+        f_flat, m_flat, d_flat, w_flat = packed
+    if ws is None:
+        ws = workspace_mixed(gshapes, dev)
+    _check(ws, "workspace", dtype=torch.uint8)
+    p = params(lam, theta, order, outer, iters, data_term, eps)
+    _lib.call("nadmm_register_mixed", ctypes.c_int32(len(gshapes)), _dims_array(gshapes), ctypes.byref(p),
+              _ptr(f_flat), _ptr(m_flat), _ptr(d_flat), _ptr(w_flat), _ptr(ws), ctypes.c_size_t(ws.numel()),
+              _stream())
+    disp, warped = [None] * len(shapes), [None] * len(shapes)
+    o = 0
+    for i, shp, n in zip(perm, gshapes, sizes):
+        disp[i] = d_flat[3 * o:3 * (o + n)].view((3,) + shp)
+        warped[i] = w_flat[o:o + n].view(shp)
+        o += n
+    return {"disp": disp, "warped": warped, "packed": (f_flat, m_flat, d_flat, w_flat)}
 
 
 def workspace_grad(vol_shape, lam: float, theta: float, order: int, iters: int, checkpoint: int,

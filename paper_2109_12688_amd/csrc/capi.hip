@@ -582,6 +582,74 @@ nadmm_status check_pyramid(const nadmm_dims& d, const nadmm_pyramid* pyr) {
   return NADMM_OK;
 }
 
+// ---- pairs of several sizes (one launch per phase) -----------------------
+// Pairs of one size must be consecutive (a size class); every field holds all
+// pairs back to back in the caller's order.
+struct MixedPlan {
+  MixedLaunch m{};
+  size_t v_total = 0, s_total = 0;  // sum of V, sum of half-spectrum elements
+};
+
+nadmm_status mixed_plan(int32_t npairs, const nadmm_dims* dims, MixedPlan& mp) {
+  if (npairs < 1 || npairs > kMaxMixedPairs)
+    return fail(NADMM_ERR_INVALID_ARG, "npairs must be in [1, %d] (got %d)", kMaxMixedPairs, npairs);
+  if (!dims) return fail(NADMM_ERR_INVALID_ARG, "dims is NULL");
+  MixedDesc& d = mp.m.d;
+  d.nclasses = 0;
+  for (int i = 0; i < npairs; ++i) {
+    const nadmm_dims di = dims[i];
+    CHECK(check_dims(di));
+    const Geo g = geo(di);
+    MixedClass* k = d.nclasses ? &d.c[d.nclasses - 1] : nullptr;
+    if (!k || k->g.nx != g.nx || k->g.ny != g.ny || k->g.nz != g.nz) {
+      for (int c = 0; c + 1 < d.nclasses; ++c)
+        if (d.c[c].g.nx == g.nx && d.c[c].g.ny == g.ny && d.c[c].g.nz == g.nz)
+          return fail(NADMM_ERR_INVALID_ARG, "pair %d: pairs of one size must be consecutive", i);
+      if (d.nclasses == kMaxClasses)
+        return fail(NADMM_ERR_INVALID_ARG, "more than %d different sizes in one mixed batch", kMaxClasses);
+      if (!mixed_class_ok(g))
+        return fail(NADMM_ERR_UNSUPPORTED_SIZE,
+                    "dims (%d, %d, %d) of pair %d: a mixed batch needs nx in {64, 96, 128, 192} and ny, nz in "
+                    "{32, 64, 96, 128}", di.nx, di.ny, di.nz, i);
+      k = &d.c[d.nclasses++];
+      *k = MixedClass{};
+      k->g = g;
+      k->o1 = (int64_t)mp.v_total;
+      k->os = (int64_t)mp.s_total;
+    }
+    k->npairs += 1;
+    mp.v_total += (size_t)g.V;
+    mp.s_total += (size_t)3 * (g.nx / 2 + 1) * g.ny * g.nz;
+  }
+  mixed_shapes(mp.m);
+  return NADMM_OK;
+}
+
+// Workspace of a mixed batch: each class's transform tables, then r, I1^w,
+// s^k, s^{k-1}, the half spectrum and the displacement ping-pong buffer of
+// every pair.
+struct MixedLayout {
+  size_t tab[kMaxClasses], r, iw, s1, s2, X, u, total;
+};
+
+MixedLayout mixed_layout(const MixedPlan& mp) {
+  MixedLayout L{};
+  const size_t V = mp.v_total;
+  size_t o = 0;
+  for (int c = 0; c < mp.m.d.nclasses; ++c) {
+    L.tab[c] = o;
+    o += align256(tables_bytes(mp.m.d.c[c].g));
+  }
+  L.r = o; o += align256(V * sizeof(float));
+  L.iw = o; o += align256(V * sizeof(float));
+  L.s1 = o; o += align256(3 * V * sizeof(float));
+  L.s2 = o; o += align256(3 * V * sizeof(float));
+  L.X = o; o += align256(mp.s_total * sizeof(float2));
+  L.u = o; o += align256(3 * V * sizeof(float));
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -678,6 +746,90 @@ nadmm_status nadmm_register_batch(nadmm_dims d, int32_t batch, const nadmm_param
   CHECK(check_batch(batch));
   return register_impl(d, p, fixed, moving, init_disp, disp, warped, nullptr, workspace,
                        workspace_bytes, stream, batch);
+}
+
+nadmm_status nadmm_workspace_size_mixed(int32_t npairs, const nadmm_dims* dims, size_t* bytes) {
+  MixedPlan mp;
+  CHECK(mixed_plan(npairs, dims, mp));
+  if (!bytes) return fail(NADMM_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = mixed_layout(mp).total;
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_register_mixed(int32_t npairs, const nadmm_dims* dims, const nadmm_params* p,
+                                  const float* fixed, const float* moving, float* disp, float* warped,
+                                  void* workspace, size_t workspace_bytes, void* stream) {
+  MixedPlan mp;
+  CHECK(mixed_plan(npairs, dims, mp));
+  CHECK(check_params(p, true));
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(warped, "warped", true));
+  CHECK(check_ptr(workspace, "workspace", false));
+  const MixedLayout L = mixed_layout(mp);
+  if (workspace_bytes < L.total)
+    return fail(NADMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                workspace_bytes, L.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t V = mp.v_total;
+  if (p->outer == 0) {  // no warping: zero displacement, the moving image as warped
+    HIP_TRY(timed(KK_FILL, st, [&] { return launch_fill(disp, 0.0f, 3 * V, st); }));
+    if (warped) HIP_TRY(hipMemcpyAsync(warped, moving, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return NADMM_OK;
+  }
+  MixedLaunch& m = mp.m;
+  for (int c = 0; c < m.d.nclasses; ++c) m.d.c[c].tab = tables_at(m.d.c[c].g, at<char>(workspace, L.tab[c]));
+  HIP_TRY(launch_mixed_tables(m, st));
+  float* r = at<float>(workspace, L.r);
+  float* iw = at<float>(workspace, L.iw);
+  float* S1 = at<float>(workspace, L.s1);
+  float* S2 = at<float>(workspace, L.s2);
+  float2* X = at<float2>(workspace, L.X);
+  float* U = at<float>(workspace, L.u);
+  const std::vector<double> gam = nesterov_gammas(p->iters);
+  const float lam = (float)p->lambda, theta = (float)p->theta, eps = (float)p->eps;
+  // the same sequence as nadmm_register from u = 0, every launch over all pairs
+  auto dst_of = [&](int c) { return ((p->outer - 1 - c) % 2 == 0) ? disp : U; };
+  const float* u_src = nullptr;
+  for (int c = 0; c < p->outer; ++c) {
+    const bool last = (c == p->outer - 1);
+    const float* iw_c = c == 0 ? moving : iw;
+    HIP_TRY(timed(KK_PASS_A, st, [&] {
+      return launch_mixed_pass_a0(m, iw_c, fixed, r, S1, theta, eps, p->data_term, X, st);
+    }));
+    HIP_TRY(timed(KK_PASS_B, st, [&] { return launch_mixed_pass_b(m, X, lam, theta, p->order, st); }));
+    float* cur = S1;
+    float* prev = S2;
+    for (int k = 1; k < p->iters; ++k) {
+      PassCArgs a{};
+      a.X = X;
+      a.s1 = cur;
+      a.s2 = (k == 1) ? nullptr : prev;
+      a.gamma = (float)gam[k - 1];
+      a.gamma_next = (k + 1 < p->iters) ? (float)gam[k] : 0.0f;
+      a.iw = iw_c;
+      a.r = r;
+      a.theta = theta;
+      a.eps = eps;
+      a.data_term = p->data_term;
+      a.out = prev;
+      HIP_TRY(timed(KK_PASS_CA_ITER, st, [&] { return launch_mixed_pass_c(m, kIterFwdIw, a, st); }));
+      HIP_TRY(timed(KK_PASS_B, st, [&] { return launch_mixed_pass_b(m, X, lam, theta, p->order, st); }));
+      float* t = cur;
+      cur = prev;
+      prev = t;
+    }
+    PassCArgs a{};
+    a.X = X;
+    a.out = dst_of(c);
+    a.u_old = u_src;
+    a.img = moving;
+    a.iw_out = last ? warped : iw;
+    HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_mixed_pass_c(m, kCompose, a, st); }));
+    u_src = a.out;
+  }
+  return NADMM_OK;
 }
 
 nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, void* workspace,

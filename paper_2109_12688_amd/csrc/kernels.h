@@ -173,4 +173,62 @@ int jacobian_blocks(const Geo& g);
 hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* partial,
                            double* stats, int64_t* n_nonpos, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Pairs of several sizes in one launch per phase.  A mixed launch covers every
+// pair of every size: its workgroups are numbered over (size class, pair,
+// tile); each finds its class in the descriptor (a kernel argument) and runs
+// the same device code as the one-size launch compiled for that class's
+// sizes.  Pairs of one size are consecutive, and every field holds all pairs
+// back to back, so a pair's data sits at its class's offset plus its index in
+// the class times the per-pair size.
+// ---------------------------------------------------------------------------
+constexpr int kMaxClasses = 8;
+constexpr int kMaxMixedPairs = 4096;
+struct MixedClass {
+  Geo g;
+  XDivs xd;
+  int64_t o1, os;      // element offsets of the class's first pair: scalar volumes
+                       // (vector fields at 3 o1) and half spectra (complex)
+  int ls, rs;          // x-line LDS line stride, y-z plane row stride
+  int nby;             // x-line tiles along y per z-slice (ny / rows)
+  int xtile0, ptile0;  // first workgroup of the class in x-line and plane launches
+  int xtiles;          // x-line workgroups per pair: nby * nz
+  int pplanes;         // y-z planes per pair: 3 (nx / 2 + 1)
+  int pgroup, psub;    // planes per plane-launch workgroup, and the threads of each
+  int plds;            // LDS bytes of one plane's group
+  int npairs;
+  Tables tab;
+};
+struct MixedDesc {
+  int nclasses;
+  int xtiles, ptiles;  // workgroups of an x-line and of a plane launch
+  MixedClass c[kMaxClasses];
+};
+// A mixed batch's descriptor and the launch shapes (threads, LDS) that fit
+// every class.
+struct MixedLaunch {
+  MixedDesc d;
+  int xthreads, pthreads;
+  size_t xlds, plds;
+};
+// True when a class of these sizes can take part in a mixed launch: lengths
+// with compile-time transforms (nx in {64, 96, 128, 192}, ny and nz in
+// {32, 64, 96, 128}) and a y-z plane in one workgroup.
+bool mixed_class_ok(const Geo& g);
+// Launch shapes of the mixed launches: threads and LDS that fit every class;
+// a plane-launch workgroup transforms several planes of a class at once (one
+// thread group and LDS region each) when they fit.  Needs the classes' g and
+// npairs; sets their plane fields and ptile0 and the totals.
+void mixed_shapes(MixedLaunch& m);
+hipError_t launch_mixed_tables(const MixedLaunch& m, hipStream_t st);
+hipError_t launch_mixed_pass_a0(const MixedLaunch& m, const float* iw, const float* ref, float* r,
+                                float* s0, float theta, float eps, int data_term, float2* X,
+                                hipStream_t st);
+hipError_t launch_mixed_pass_b(const MixedLaunch& m, float2* X, float lambda, float theta, int order,
+                               hipStream_t st);
+// mode kIterFwdIw or kCompose; the pointers of `a` are the fields' bases.
+hipError_t launch_mixed_pass_c(const MixedLaunch& m, PassCMode mode, const PassCArgs& a,
+                               hipStream_t st);
+int xline_stride_of(int nx);
+
 }  // namespace nadmm

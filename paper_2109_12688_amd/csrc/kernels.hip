@@ -25,6 +25,7 @@
 // (mode kIterFwd): the new state is extrapolated and transformed along x on
 // the same lines without leaving the chip.
 #include <float.h>
+#include <string.h>
 
 #include <map>
 #include <mutex>
@@ -85,12 +86,19 @@ size_t plane_lds_bytes(const Geo& g, int rs) {
          sizeof(float2) * (size_t)g.nz * rs;
 }
 
-int xline_threads(const Geo& g) {
-  const int elems = 3 * (xline_rows(g) / 2) * g.nx;
+static int xline_threads_rows(const Geo& g, int rows) {
+  const int elems = 3 * (rows / 2) * g.nx;
   int t = round_up((elems + 7) / 8, 64);
   if (t > 1024) t = 1024;
   if (t < 64) t = 64;
   return t;
+}
+int xline_threads(const Geo& g) { return xline_threads_rows(g, xline_rows(g)); }
+
+// The x-line bounds of launch_shape_ok for `rows` rows and `xt` threads.
+static bool xline_rows_fit(const Geo& g, int rows, int xt) {
+  return g.ny % rows == 0 && rows % 2 == 0 && 3 * (rows / 2) * g.nx <= kEpt * xt &&
+         3 * rows * (g.nx / 4) <= kXItems * xt && rows * (g.nx / 4) <= 2 * xt && 3 * rows * g.nx < 65536;
 }
 
 constexpr int kPlaneEptTarget = 8;  // points per thread the plane pass is sized for
@@ -212,8 +220,7 @@ bool launch_shape_ok(const Geo& g) {
   return fft_a && load_a && point_c && pass_b && div_x;
 }
 
-XDivs make_xdivs(const Geo& g) {
-  const int yb = xline_rows(g);
+static XDivs make_xdivs_rows(const Geo& g, int yb) {
   XDivs d;
   d.q4 = make_fastdiv(g.nx / 4);
   d.yb = make_fastdiv(yb);
@@ -224,6 +231,7 @@ XDivs make_xdivs(const Geo& g) {
   d.nz = make_fastdiv(g.nz);
   return d;
 }
+XDivs make_xdivs(const Geo& g) { return make_xdivs_rows(g, xline_rows(g)); }
 
 // ---------------------------------------------------------------------------
 // elementwise kernels
@@ -493,9 +501,9 @@ Tables tables_at(const Geo& g, void* base) {
   return t;
 }
 
-__global__ void k_tables(Geo g, Tables t) {
+__device__ __forceinline__ void tables_body(const Geo& g, const Tables& t, int bx, int gx) {
   const int n_all = g.nx + g.ny + g.nz + (g.nx / 2 + 1) + g.ny + g.nz;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_all; i += gridDim.x * blockDim.x) {
+  for (int i = bx * blockDim.x + threadIdx.x; i < n_all; i += gx * blockDim.x) {
     int k = i;
     float2* tw = nullptr;
     float* sv = nullptr;
@@ -517,6 +525,8 @@ __global__ void k_tables(Geo g, Tables t) {
   }
 }
 
+__global__ void k_tables(Geo g, Tables t) { tables_body(g, t, blockIdx.x, gridDim.x); }
+
 hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st) {
   hipLaunchKernelGGL(k_tables, dim3(4), dim3(256), 0, st, g, t);
   return hipGetLastError();
@@ -526,15 +536,27 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st) {
 // pass A: t -> x half spectrum
 // X layout: X[((c * (nx/2 + 1) + p) * nz + z) * ny + y], p <= nx/2.
 // ---------------------------------------------------------------------------
+// Coordinates of a workgroup's tile: its block index and grid extent in an
+// ordinary launch (of_block), or the ones a mixed-size launch decodes for it.
+// z is the pair within a batch of one size; remap: x-line tiles may be
+// reordered for the XCDs (see xline_tile).
+struct Blk {
+  int x, y, z, gx, gy;
+  bool remap;
+  __device__ static Blk of_block() {
+    return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y, true};
+  }
+};
+
 // Tile (y-block, z) of an x-line workgroup.  Workgroups are dispatched
 // round-robin over the 8 XCDs, each with its own L2; when the grid allows,
 // each XCD gets one contiguous range of tiles instead, so that neighbouring
 // tiles (which share 128-byte lines of the half spectrum, and z-planes for
 // the gathers) meet in the same L2.
-__device__ __forceinline__ void xline_tile(int& by, int& z) {
-  const int nby = gridDim.x, n = gridDim.x * gridDim.y;
-  int l = blockIdx.x + nby * blockIdx.y;
-  if ((n & 7) == 0) l = (l & 7) * (n >> 3) + (l >> 3);
+__device__ __forceinline__ void xline_tile(const Blk& bk, int& by, int& z) {
+  const int nby = bk.gx, n = bk.gx * bk.gy;
+  int l = bk.x + nby * bk.y;
+  if (bk.remap && (n & 7) == 0) l = (l & 7) * (n >> 3) + (l >> 3);
   z = l / nby;
   by = l - z * nby;
 }
@@ -602,7 +624,7 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
   float2* tw = lds;
   float2* buf = lds + nx;
   int by, z;
-  xline_tile(by, z);
+  xline_tile(Blk::of_block(), by, z);
   const int y0 = by * yb;
   const int nthr = blockDim.x;
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
@@ -652,10 +674,10 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
   store_half_spectrum<NX>(g, xd, ls, buf, X, y0, z);
 }
 
-static size_t pass_a_lds(const Geo& g) {
-  const int yb = xline_rows(g);
+static size_t pass_a_lds_rows(const Geo& g, int yb) {
   return sizeof(float2) * ((size_t)g.nx + (size_t)3 * (yb / 2) * xline_stride(g.nx));
 }
+static size_t pass_a_lds(const Geo& g) { return pass_a_lds_rows(g, xline_rows(g)); }
 
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
                          const float* s2, float gamma, float2* X, hipStream_t st, int batch) {
@@ -743,10 +765,15 @@ struct PlansCT {
 // NY = NZ = 0: any size (run-time plans); otherwise the sizes are fixed.
 // DERIV: multiply by d/dlambda of the multiplier (generic kernel only).
 template <int NY, int NZ, bool DERIV = false>
-__global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan pz0, TeamPlan pzi0,
-                                                 XDivs xd, int rs_host, Tables tg, float2* __restrict__ X,
-                                                 float lambda, float theta, int order) {
-  extern __shared__ float2 lds[];
+// tid, nthr: the thread's index within, and the size of, the thread group
+// that transforms this plane (the whole workgroup, or one of several groups
+// sharing it, each with its own LDS at lds); every group of a workgroup
+// meets the same __syncthreads() barriers.
+__device__ __forceinline__ void pass_b_body(const Geo& g, const TeamPlan& py0, const TeamPlan& pz0,
+                                            const TeamPlan& pzi0, const XDivs& xd, int rs_host,
+                                            const Tables& tg, float2* __restrict__ X, float lambda,
+                                            float theta, int order, const Blk& bk, int tid, int nthr,
+                                            float2* lds) {
   using PCT = PlansCT<NY ? NY : 32, NZ ? NZ : 32>;
   // compile-time sizes: the same row stride as the host's, as a constant
   constexpr int kRs = NY ? plane_row_stride_ce(NY ? NY : 32, NZ ? NZ : 32, PCT::PY, PCT::PZ) : 0;
@@ -759,15 +786,14 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   if constexpr (NY == 0) pol = PlansRT{plans, plans + 1, plans + 2};
   // plane element (z, y) at z * rs + y + y / 16 (host-chosen rs)
   const int ny = NY ? NY : g.ny, nz = NZ ? NZ : g.nz, np = g.nx / 2 + 1;
-  const int nthr = blockDim.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = nthr >> 6;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
   float2* twy = lds;
   float2* twz = twy + ny;
   float* sy = reinterpret_cast<float*>(twz + nz);
   float* sz = sy + ny;
   float2* buf = reinterpret_cast<float2*>(sz + nz + ((ny + nz) & 1));  // keep 8-byte alignment
-  const int p = blockIdx.x, c = blockIdx.y;
-  float2* plane = at_pair(X, spectrum_elems(g), blockIdx.z) + (size_t)(c * np + p) * nz * ny;
+  const int p = bk.x, c = bk.y;
+  float2* plane = at_pair(X, spectrum_elems(g), bk.z) + (size_t)(c * np + p) * nz * ny;
   const float4* plane4 = reinterpret_cast<const float4*>(plane);
   // the x transform of pass A already carries 1 / nx of the inverse's 1 / V
   const float inv_v = 1.0f / (float)(ny * nz);
@@ -807,7 +833,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
   {
     float2 t2 = make_float2(0.f, 0.f);
     float t1 = 0.f;
-    const int ti = threadIdx.x;
+    const int ti = tid;
     if (ti < ny) {
       t2 = tg.twy[ti];
       t1 = tg.sy[ti];
@@ -819,7 +845,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
     const int l0 = wave * nlw_y;
     int items = 0;
     if (l0 < nz) items = load_rows(l0, 0, v);
-    if (NY == 0 && threadIdx.x == 0) {
+    if (NY == 0 && tid == 0) {
       plans[0] = py0;
       plans[1] = pz0;
       plans[2] = pzi0;
@@ -831,7 +857,7 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
       twz[ti - ny] = t2;
       sz[ti - ny] = t1;
     }
-    for (int i = ny + nz + threadIdx.x; i < 2 * (ny + nz); i += nthr) {  // blocks narrower than ny + nz
+    for (int i = ny + nz + tid; i < 2 * (ny + nz); i += nthr) {  // blocks narrower than ny + nz
       const int k = i - (ny + nz);
       if (k < ny) {
         twy[k] = tg.twy[k];
@@ -908,6 +934,15 @@ __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan p
       }
     }
   }
+}
+
+template <int NY, int NZ, bool DERIV = false>
+__global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan pz0, TeamPlan pzi0,
+                                                 XDivs xd, int rs_host, Tables tg, float2* __restrict__ X,
+                                                 float lambda, float theta, int order) {
+  extern __shared__ float2 lds[];
+  pass_b_body<NY, NZ, DERIV>(g, py0, pz0, pzi0, xd, rs_host, tg, X, lambda, theta, order, Blk::of_block(),
+                             threadIdx.x, blockDim.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1170,24 +1205,24 @@ __device__ __forceinline__ void run_gradient(const Geo& g, int nx, const float* 
 // r = I1^w - I0 and s^0 = the data step from zero, stored (the first
 // iteration reads both) and transformed along x as pass A transforms s^0.
 template <int NX, typename T>
-__global__ void __launch_bounds__(768) k_pass_a0(Geo g, FftPlan px, XDivs xd, int ls,
-                                                 const float2* __restrict__ twx,
-                                                 const float* __restrict__ iw,
-                                                 const T* __restrict__ ref, float* __restrict__ r_out,
-                                                 float* __restrict__ s0, float theta, float eps,
-                                                 int data_term, float2* __restrict__ X) {
+__device__ __forceinline__ void pass_a0_body(const Geo& g, const FftPlan& px, const XDivs& xd, int ls,
+                                             const float2* __restrict__ twx,
+                                             const float* __restrict__ iw,
+                                             const T* __restrict__ ref, float* __restrict__ r_out,
+                                             float* __restrict__ s0, float theta, float eps,
+                                             int data_term, float2* __restrict__ X, const Blk& bk) {
   extern __shared__ float2 lds[];
   const int nx = NX ? NX : g.nx, q4 = nx / 4;
-  iw = at_pair(iw, (size_t)g.V, blockIdx.z);
-  ref = at_pair(ref, (size_t)g.V, blockIdx.z);
-  r_out = at_pair(r_out, (size_t)g.V, blockIdx.z);
-  s0 = at_pair(s0, 3 * (size_t)g.V, blockIdx.z);
-  X = at_pair(X, spectrum_elems(g), blockIdx.z);
+  iw = at_pair(iw, (size_t)g.V, bk.z);
+  ref = at_pair(ref, (size_t)g.V, bk.z);
+  r_out = at_pair(r_out, (size_t)g.V, bk.z);
+  s0 = at_pair(s0, 3 * (size_t)g.V, bk.z);
+  X = at_pair(X, spectrum_elems(g), bk.z);
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   float2* tw = lds;
   float2* buf = lds + nx;
   int by, z;
-  xline_tile(by, z);
+  xline_tile(bk, by, z);
   const int y0 = by * yb;
   const int nthr = blockDim.x;
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
@@ -1228,6 +1263,16 @@ __global__ void __launch_bounds__(768) k_pass_a0(Geo g, FftPlan px, XDivs xd, in
   store_half_spectrum<NX>(g, xd, ls, buf, X, y0, z);
 }
 
+template <int NX, typename T>
+__global__ void __launch_bounds__(768) k_pass_a0(Geo g, FftPlan px, XDivs xd, int ls,
+                                                 const float2* __restrict__ twx,
+                                                 const float* __restrict__ iw,
+                                                 const T* __restrict__ ref, float* __restrict__ r_out,
+                                                 float* __restrict__ s0, float theta, float eps,
+                                                 int data_term, float2* __restrict__ X) {
+  pass_a0_body<NX, T>(g, px, xd, ls, twx, iw, ref, r_out, s0, theta, eps, data_term, X, Blk::of_block());
+}
+
 template <typename T>
 static hipError_t pass_a0_any(const Geo& g, const FftPlan& px, const Tables& t, const float* iw,
                               const T* ref, float* r, float* s0, float theta, float eps,
@@ -1263,12 +1308,12 @@ hipError_t launch_pass_a0(const Geo& g, const FftPlan& px, const Tables& t, cons
 }
 
 template <int MODE, int NX>
-__global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
-                                                const float2* __restrict__ twx, PassCArgs a) {
+__device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, const XDivs& xd, int ls,
+                                            const float2* __restrict__ twx, PassCArgs a, const Blk& bk) {
   extern __shared__ float2 lds[];
   const int nx = NX ? NX : g.nx, nh = nx / 2, q4 = nx / 4;
   {
-    const int b = blockIdx.z;
+    const int b = bk.z;
     const size_t v1 = g.V, v3 = 3 * (size_t)g.V;
     a.X = at_pair(a.X, spectrum_elems(g), b);
     a.s1 = at_pair(a.s1, v3, b);
@@ -1290,7 +1335,7 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
   float2* tw = lds;
   float2* buf = lds + nx;
   int by, z;
-  xline_tile(by, z);
+  xline_tile(bk, by, z);
   const int y0 = by * yb;
 
   // unpack two rows' half spectra into one complex row: Z = Xa + i Xb
@@ -1485,6 +1530,12 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
   }
 }
 
+template <int MODE, int NX>
+__global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
+                                                const float2* __restrict__ twx, PassCArgs a) {
+  pass_c_body<MODE, NX>(g, px, xd, ls, twx, a, Blk::of_block());
+}
+
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
                          const PassCArgs& a, hipStream_t st, int batch) {
   const int yb = xline_rows(g);
@@ -1602,6 +1653,252 @@ hipError_t launch_jacobian(const Geo& g, const float* disp, float* det, double* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_jac_final, dim3(1), dim3(256), 0, st, nb, g.V, part, stats, n_nonpos);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// mixed-size launches: one launch per phase over pairs of several sizes
+// ---------------------------------------------------------------------------
+bool mixed_class_ok(const Geo& g) {
+  const auto x_ok = [](int n) { return n == 64 || n == 96 || n == 128 || n == 192; };
+  const auto yz_ok = [](int n) { return n == 32 || n == 64 || n == 96 || n == 128; };
+  return x_ok(g.nx) && yz_ok(g.ny) && yz_ok(g.nz) && launch_shape_ok(g) && plane_fits(g);
+}
+int xline_stride_of(int nx) { return xline_stride(nx); }
+
+void mixed_shapes(MixedLaunch& m) {
+  MixedDesc& d = m.d;
+  // x-line launch: the threads of the class that needs most (each with its
+  // tuned rows); every other class then takes the rows (an even divisor of ny
+  // within the kernels' bounds) whose workgroup needs the threads closest to
+  // that number from below, so that few threads idle (results do not depend
+  // on the rows)
+  m.xthreads = 64;
+  int waves = 1;
+  for (int c = 0; c < d.nclasses; ++c) {
+    const Geo& g = d.c[c].g;
+    const int xth = xline_threads(g), pw = plane_team_threads(g) / 64;
+    if (xth > m.xthreads) m.xthreads = xth;
+    if (pw > waves) waves = pw;
+  }
+  m.xlds = 0;
+  int xt = 0;
+  for (int c = 0; c < d.nclasses; ++c) {
+    MixedClass& k = d.c[c];
+    const Geo& g = k.g;
+    int rows = xline_rows(g), best = xline_threads_rows(g, rows);
+    for (int r = 2; r <= 32; r += 2) {  // the autotuner's range
+      const int t = xline_threads_rows(g, r);
+      if (t <= m.xthreads && t > best && xline_rows_fit(g, r, m.xthreads)) {
+        best = t;
+        rows = r;
+      }
+    }
+    const size_t xl = pass_a_lds_rows(g, rows);
+    if (xl > m.xlds) m.xlds = xl;
+    k.xd = make_xdivs_rows(g, rows);
+    k.ls = xline_stride(g.nx);
+    k.rs = plane_row_stride(g);
+    k.nby = g.ny / rows;
+    k.xtiles = k.nby * g.nz;
+    k.xtile0 = xt;
+    xt += k.xtiles * k.npairs;
+  }
+  d.xtiles = xt;
+  // plane launch: `waves` wavefronts per workgroup (the largest class's need
+  // rounded up to a power of two, so that smaller classes' planes can share a
+  // workgroup), split into the largest number of equal groups that each hold
+  // a class's plane (its wavefronts and LDS)
+  int w2 = 1;
+  while (w2 < waves) w2 *= 2;
+  if (d.nclasses > 1) waves = w2 > 16 ? 16 : w2;  // measured: a little faster with several classes
+  m.pthreads = 64 * waves;
+  m.plds = 0;
+  int pt = 0;
+  for (int c = 0; c < d.nclasses; ++c) {
+    MixedClass& k = d.c[c];
+    const int need = plane_team_threads(k.g) / 64;
+    const size_t lds1 = (pass_b_lds(k.g) + 15) / 16 * 16;
+    int grp = 1;
+    for (int gcount = waves; gcount >= 1; --gcount)
+      if (waves % gcount == 0 && waves / gcount >= need && gcount * lds1 <= (size_t)kMaxLds) {
+        grp = gcount;
+        break;
+      }
+    k.pplanes = 3 * (k.g.nx / 2 + 1);
+    k.pgroup = grp;
+    k.psub = m.pthreads / grp;
+    k.plds = (int)lds1;
+    k.ptile0 = pt;
+    pt += (k.npairs * k.pplanes + grp - 1) / grp;
+    if (grp * lds1 > m.plds) m.plds = grp * lds1;
+  }
+  d.ptiles = pt;
+}
+
+// The class of workgroup l of an x-line (plane = false) or plane launch:
+// classes are numbered in the order of their first workgroups.
+__device__ __forceinline__ int mixed_class_of(const MixedDesc& md, int l, bool plane) {
+  int c = 0;
+#pragma unroll
+  for (int k = 1; k < kMaxClasses; ++k)
+    if (k < md.nclasses && l >= (plane ? md.c[k].ptile0 : md.c[k].xtile0)) c = k;
+  return c;
+}
+
+template <typename P>
+__device__ __forceinline__ P* off_by(P* p, int64_t o) {
+  return p ? p + o : p;
+}
+
+// Decodes an x-line workgroup of a mixed launch: class, pair index within the
+// class and the tile within the pair.  Within each class (a contiguous range
+// of workgroups, dispatched round-robin over the XCDs) the workgroups are
+// reordered so that each XCD gets one contiguous range of (pair, tile), as
+// in the one-size launches; every class is spread over all XCDs, whose work
+// then stays balanced although tiles of different classes differ in size.
+struct MixedTile {
+  int cls, pair;
+  Blk bk;
+};
+__device__ __forceinline__ MixedTile mixed_xline_tile(const MixedDesc& md) {
+  const int l = blockIdx.x;
+  MixedTile t;
+  t.cls = mixed_class_of(md, l, false);
+  const MixedClass& mc = md.c[t.cls];
+  const int n = mc.xtiles * mc.npairs;
+  int local = l - mc.xtile0;
+  if ((n & 7) == 0 && (mc.xtile0 & 7) == 0) local = (local & 7) * (n >> 3) + (local >> 3);
+  t.pair = local / mc.xtiles;
+  t.bk = Blk{local - t.pair * mc.xtiles, 0, 0, mc.nby, mc.g.nz, false};
+  return t;
+}
+
+__global__ void k_mixed_tables(const MixedDesc md) {
+  const MixedClass& mc = md.c[blockIdx.y];
+  tables_body(mc.g, mc.tab, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(768) k_mixed_pass_a0(const MixedDesc md, const float* __restrict__ iw,
+                                                       const float* __restrict__ ref, float* __restrict__ r,
+                                                       float* __restrict__ s0, float theta, float eps,
+                                                       int data_term, float2* __restrict__ X) {
+  const MixedTile t = mixed_xline_tile(md);
+  const MixedClass& mc = md.c[t.cls];
+  const Geo g = mc.g;
+  const XDivs xd = mc.xd;
+  const FftPlan px{};  // the compile-time x plans need none
+  const int64_t o1 = mc.o1 + (int64_t)t.pair * g.V;
+  iw += o1;
+  ref += o1;
+  r += o1;
+  s0 += 3 * o1;
+  X += mc.os + (int64_t)t.pair * (int64_t)spectrum_elems(g);
+#define NADMM_MIXED_A0(N)                                                                                \
+  case N:                                                                                                \
+    pass_a0_body<N, float>(g, px, xd, mc.ls, mc.tab.twx, iw, ref, r, s0, theta, eps, data_term, X, t.bk); \
+    break;
+  switch (g.nx) {
+    NADMM_MIXED_A0(64) NADMM_MIXED_A0(96) NADMM_MIXED_A0(128) NADMM_MIXED_A0(192)
+  }
+#undef NADMM_MIXED_A0
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(768) k_mixed_pass_c(const MixedDesc md, PassCArgs a) {
+  const MixedTile t = mixed_xline_tile(md);
+  const MixedClass& mc = md.c[t.cls];
+  const Geo g = mc.g;
+  const XDivs xd = mc.xd;
+  const FftPlan px{};
+  const int64_t o1 = mc.o1 + (int64_t)t.pair * g.V, o3 = 3 * o1;
+  a.X = off_by(a.X, mc.os + (int64_t)t.pair * (int64_t)spectrum_elems(g));
+  a.s1 = off_by(a.s1, o3);
+  a.s2 = off_by(a.s2, o3);
+  a.J = off_by(a.J, o3);
+  a.iw = off_by(a.iw, o1);
+  a.r = off_by(a.r, o1);
+  a.out = off_by(a.out, o3);
+  a.v_out = off_by(a.v_out, o3);
+  a.b_out = off_by(a.b_out, o3);
+  a.u_old = off_by(a.u_old, o3);
+  a.img = off_by(a.img, o1);
+  a.img_bf16 = off_by(a.img_bf16, o1);
+  a.iw_out = off_by(a.iw_out, o1);
+  a.vel_out = off_by(a.vel_out, o3);
+#define NADMM_MIXED_C(N)                                              \
+  case N:                                                             \
+    pass_c_body<MODE, N>(g, px, xd, mc.ls, mc.tab.twx, a, t.bk);      \
+    break;
+  switch (g.nx) {
+    NADMM_MIXED_C(64) NADMM_MIXED_C(96) NADMM_MIXED_C(128) NADMM_MIXED_C(192)
+  }
+#undef NADMM_MIXED_C
+}
+
+__global__ void __launch_bounds__(1024) k_mixed_pass_b(const MixedDesc md, float2* __restrict__ X,
+                                                       float lambda, float theta, int order) {
+  extern __shared__ float2 lds[];
+  const int l = blockIdx.x;
+  const MixedClass& mc = md.c[mixed_class_of(md, l, true)];
+  const Geo g = mc.g;
+  const XDivs xd = mc.xd;
+  const Tables tab = mc.tab;
+  // planes pgroup * (l - ptile0) ... of the class, one per thread group; a
+  // group past the class's last plane repeats that plane (the same reads
+  // before the first barrier and the same values written after the last)
+  const int sub = threadIdx.x / mc.psub, tid = threadIdx.x - sub * mc.psub;
+  const int total = mc.npairs * mc.pplanes;
+  int q = (l - mc.ptile0) * mc.pgroup + sub;
+  if (q >= total) q = total - 1;
+  const int j = q / mc.pplanes, tl = q - j * mc.pplanes;
+  const int np = g.nx / 2 + 1, c = tl / np;
+  const Blk bk{tl - c * np, c, 0, 0, 0, false};
+  X += mc.os + (int64_t)j * (int64_t)spectrum_elems(g);
+  float2* mine = lds + (size_t)sub * (mc.plds / sizeof(float2));
+  const TeamPlan none{};  // the compile-time plane plans need none
+#define NADMM_MIXED_B(NY_, NZ_)                                                                          \
+  case (NY_ << 16) | NZ_:                                                                                \
+    pass_b_body<NY_, NZ_>(g, none, none, none, xd, mc.rs, tab, X, lambda, theta, order, bk, tid, mc.psub, \
+                          mine);                                                                         \
+    break;
+  switch ((g.ny << 16) | g.nz) {
+    NADMM_MIXED_B(32, 32) NADMM_MIXED_B(32, 64) NADMM_MIXED_B(32, 96) NADMM_MIXED_B(32, 128)
+    NADMM_MIXED_B(64, 32) NADMM_MIXED_B(64, 64) NADMM_MIXED_B(64, 96) NADMM_MIXED_B(64, 128)
+    NADMM_MIXED_B(96, 32) NADMM_MIXED_B(96, 64) NADMM_MIXED_B(96, 96) NADMM_MIXED_B(96, 128)
+    NADMM_MIXED_B(128, 32) NADMM_MIXED_B(128, 64) NADMM_MIXED_B(128, 96) NADMM_MIXED_B(128, 128)
+  }
+#undef NADMM_MIXED_B
+}
+
+hipError_t launch_mixed_tables(const MixedLaunch& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_tables, dim3(4, m.d.nclasses), dim3(256), 0, st, m.d);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_pass_a0(const MixedLaunch& m, const float* iw, const float* ref, float* r,
+                                float* s0, float theta, float eps, int data_term, float2* X,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_pass_a0, dim3(m.d.xtiles), dim3(m.xthreads), m.xlds, st, m.d, iw, ref, r, s0,
+                     theta, eps, data_term, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_pass_b(const MixedLaunch& m, float2* X, float lambda, float theta, int order,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_pass_b, dim3(m.d.ptiles), dim3(m.pthreads), m.plds, st, m.d, X, lambda, theta,
+                     order);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_pass_c(const MixedLaunch& m, PassCMode mode, const PassCArgs& a,
+                               hipStream_t st) {
+  if (mode == kIterFwdIw)
+    hipLaunchKernelGGL(k_mixed_pass_c<kIterFwdIw>, dim3(m.d.xtiles), dim3(m.xthreads), m.xlds, st, m.d, a);
+  else if (mode == kCompose)
+    hipLaunchKernelGGL(k_mixed_pass_c<kCompose>, dim3(m.d.xtiles), dim3(m.xthreads), m.xlds, st, m.d, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
