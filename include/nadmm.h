@@ -20,8 +20,8 @@
  * Alignment. Every array pointer must be 16-byte aligned.
  * Streams.   `stream` is a hipStream_t passed as void* (NULL = the null
  *           stream).  Every call except nadmm_register_threshold,
- *           nadmm_register_pyramid_threshold and nadmm_autotune (which wait
- *           for their own results) only enqueues
+ *           nadmm_register_pyramid_threshold, nadmm_register_checked and
+ *           nadmm_autotune (which wait for their own results) only enqueues
  *           work on that stream and returns; results are valid after the
  *           caller synchronises it.
  * Errors.   Every entry point validates all arguments before it enqueues
@@ -51,7 +51,9 @@ typedef enum {
   NADMM_ERR_INVALID_ARG = 1,      /* null/misaligned pointer, bad parameter value   */
   NADMM_ERR_UNSUPPORTED_SIZE = 2, /* dimensions outside the supported set above      */
   NADMM_ERR_WORKSPACE = 3,        /* workspace missing or smaller than required      */
-  NADMM_ERR_HIP = 4               /* a HIP runtime call failed (message in last_error) */
+  NADMM_ERR_HIP = 4,              /* a HIP runtime call failed (message in last_error) */
+  NADMM_ERR_NONFINITE = 5,        /* nadmm_register_checked: NaN or infinity in the outputs */
+  NADMM_ERR_DIVERGED = 6          /* nadmm_register_checked: an ADMM loop diverged (guard) */
 } nadmm_status;
 
 typedef struct {
@@ -120,6 +122,36 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p,
                             const float* init_disp, float* disp, float* warped,
                             float* velocities, void* workspace, size_t workspace_bytes,
                             void* stream);
+
+/* nadmm_register with checks of its result, reported as status codes.
+ * flags (bit set):
+ *   NADMM_CHECK_FINITE      count NaN and infinite values of disp and warped
+ *                           on the device; any: NADMM_ERR_NONFINITE.
+ *   NADMM_CHECK_DIVERGENCE  the divergence guard of every warping with
+ *                           iters >= 3.  Eq. (5) has no restart, and the
+ *                           un-restarted momentum can diverge when the data
+ *                           term dominates (large |grad I1|, large lambda);
+ *                           the paper gives no rule, and this library reads
+ *                           divergence as: the fixed-point residual of the
+ *                           last iteration exceeds that of the first,
+ *                           |s^{K-1} - s^{K-2}| > |s^1 - s^0| (L2 norms over
+ *                           the whole field, s^k = v^k + b_hat^k the w-step's
+ *                           input, sums in FP64 in a fixed order) or is not
+ *                           finite.  Any warping: NADMM_ERR_DIVERGED (when
+ *                           the outputs are finite or not checked).
+ *   diverged   host out, p->outer int32 or NULL: 1 for each warping whose
+ *              guard tripped, else 0.
+ * The outputs are written in every case (the registration runs to its fixed
+ * counts).  Other arguments, workspace and errors as for nadmm_register (no
+ * per-warping velocities).  SYNCHRONOUS: the guard reads two sums per
+ * warping back (32 KB of pinned host memory and two events are allocated for
+ * the call) and the call waits for the stream before returning. */
+#define NADMM_CHECK_FINITE 1u
+#define NADMM_CHECK_DIVERGENCE 2u
+nadmm_status nadmm_register_checked(nadmm_dims d, const nadmm_params* p, uint32_t flags,
+                                    const float* fixed, const float* moving, const float* init_disp,
+                                    float* disp, float* warped, int32_t* diverged, void* workspace,
+                                    size_t workspace_bytes, void* stream);
 
 /* nadmm_register with threshold stopping (Sec. 4, second hyper-parameter
  * version: the ADMM loop ends at a convergence threshold, the warping loop

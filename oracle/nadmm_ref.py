@@ -220,6 +220,8 @@ class AdmmResult:
     history: list = field(default_factory=list)
     iters_run: int = 0
     rel_change: list = field(default_factory=list)  # |s^k - s^{k-1}| / |s^k|, k >= 1
+    # divergence guard: |s^{K-1} - s^{K-2}| > |s^1 - s^0| after K >= 3 iterations
+    diverged: bool = False
 
 
 def rel_change(new: np.ndarray, old: np.ndarray) -> float:
@@ -253,7 +255,12 @@ def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
     ``mult`` overrides the w-step multiplier (used only by tests that plant a
     mistake to show the pins catch it).  With ``tol`` the loop also stops
     after the first iteration k >= 1 whose w-step input s^k = v^k + b_hat^k
-    satisfies |s^k - s^{k-1}| <= tol |s^k| (threshold stopping, Sec. 4)."""
+    satisfies |s^k - s^{k-1}| <= tol |s^k| (threshold stopping, Sec. 4).
+
+    ``diverged`` (the paper gives no restart or divergence rule; this is the
+    guard's reading): after K >= 3 iterations, the fixed-point residual of
+    the last iteration exceeds that of the first, |s^{K-1} - s^{K-2}| >
+    |s^1 - s^0| in the L2 norm over the whole field (or is not finite)."""
     dims_xyz = (J.shape[3], J.shape[2], J.shape[1])
     if mult is None:
         mult = w_step_multiplier(dims_xyz, lam, theta, order)
@@ -268,6 +275,8 @@ def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
     changes = []
     stop = False
     k_run = 0
+    first_res = 0.0
+    diverged = False
     for k in range(iters):
         a = w_hat - b_hat
         if data_term == 2:
@@ -281,6 +290,11 @@ def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
         if tol is not None and s_prev is not None:
             changes.append(rel_change(s, s_prev))
             stop = below_threshold(s, s_prev, tol)
+        if k == 1:
+            first_res = float(np.sum((s - s_prev) ** 2))
+        if k == iters - 1 and k >= 2:
+            last_res = float(np.sum((s - s_prev) ** 2))
+            diverged = not math.isfinite(last_res) or last_res > first_res
         s_prev = s
         alpha_next = (1.0 + math.sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0
         g = (alpha - 1.0) / alpha_next
@@ -297,7 +311,7 @@ def admm(J: np.ndarray, r: np.ndarray, lam: float, theta: float, order: int,
         w_prev, b_prev = w, b
         alpha = alpha_next
     return AdmmResult(w=w, b=b, v=v, gammas=np.array(gam), history=hist, iters_run=k_run,
-                      rel_change=changes)
+                      rel_change=changes, diverged=diverged and k_run == iters)
 
 
 # ---------------------------------------------------------------------------
@@ -312,6 +326,7 @@ class RegisterResult:
     level_iters: list = field(default_factory=list)   # pyramid: iters_run of every level
     admm_change: list = field(default_factory=list)   # per warping: its ADMM rel_change list
     warp_change: list = field(default_factory=list)   # |u_c - u_{c-1}| / |u_c|, c >= 1
+    diverged: list = field(default_factory=list)      # the ADMM guard of each warping
 
 
 def register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float,
@@ -332,12 +347,13 @@ def register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float,
     fixed = np.asarray(fixed, dtype=np.float64)
     moving = np.asarray(moving, dtype=np.float64)
     u = np.zeros((3,) + fixed.shape) if init_disp is None else np.asarray(init_disp, np.float64).copy()
-    vels, runs, achg, wchg = [], [], [], []
+    vels, runs, achg, wchg, divs = [], [], [], [], []
     for c in range(outer):
         _, J, r = warp_grad_residual(moving, fixed, u)
         res = admm(J, r, lam, theta, order, iters, data_term=data_term, tol=tol_admm)
         runs.append(res.iters_run)
         achg.append(res.rel_change)
+        divs.append(res.diverged)
         vel = res.w
         if keep_velocities:
             vels.append(vel.copy())
@@ -348,7 +364,7 @@ def register(fixed: np.ndarray, moving: np.ndarray, lam: float, theta: float,
                 break
     warped = trilinear_periodic(moving, u)
     return RegisterResult(disp=u, warped=warped, velocities=vels, iters_run=runs, admm_change=achg,
-                          warp_change=wchg)
+                          warp_change=wchg, diverged=divs)
 
 
 # ---------------------------------------------------------------------------

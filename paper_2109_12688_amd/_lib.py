@@ -17,7 +17,9 @@ LIB_PATH = os.environ.get("NADMM_LIBRARY") or os.path.join(PKG, "libnadmm.so")
 
 NADMM_OK = 0
 STATUS_NAMES = {0: "NADMM_OK", 1: "NADMM_ERR_INVALID_ARG", 2: "NADMM_ERR_UNSUPPORTED_SIZE",
-                3: "NADMM_ERR_WORKSPACE", 4: "NADMM_ERR_HIP"}
+                3: "NADMM_ERR_WORKSPACE", 4: "NADMM_ERR_HIP", 5: "NADMM_ERR_NONFINITE",
+                6: "NADMM_ERR_DIVERGED"}
+CHECK_FINITE, CHECK_DIVERGENCE = 1, 2
 
 
 class Dims(ctypes.Structure):
@@ -51,6 +53,8 @@ _SIGS = {
                                   _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_register": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
                        ctypes.c_int),
+    "nadmm_register_checked": ([Dims, ctypes.POINTER(Params), ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P,
+                                ctypes.c_size_t, _P], ctypes.c_int),
     "nadmm_register_bf16": ([Dims, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
                              _P], ctypes.c_int),
     "nadmm_workspace_size_batch": ([Dims, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),

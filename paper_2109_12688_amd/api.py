@@ -107,6 +107,35 @@ def register(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float
     return res
 
 
+def register_checked(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
+                     outer: int, iters: int, finite: bool = True, divergence: bool = True,
+                     data_term: int = 2, eps: float = 1e-8, init_disp: torch.Tensor | None = None,
+                     ws: torch.Tensor | None = None) -> dict:
+    """nadmm_register_checked (synchronous): the registration plus its checks.
+    Returns 'disp', 'warped', 'status' (0, NADMM_ERR_NONFINITE = 5 or
+    NADMM_ERR_DIVERGED = 6; other errors raise), 'message' and 'diverged'
+    (per warping)."""
+    _check(fixed, "fixed")
+    shp = tuple(fixed.shape)
+    _check(moving, "moving", shp)
+    vshp = (3,) + shp
+    if init_disp is not None:
+        _check(init_disp, "init_disp", vshp)
+    disp = torch.empty(vshp, dtype=torch.float32, device=fixed.device)
+    warped = torch.empty(shp, dtype=torch.float32, device=fixed.device)
+    ws = _ws(shp, ws, fixed.device)
+    p = params(lam, theta, order, outer, iters, data_term, eps)
+    div = (ctypes.c_int32 * max(outer, 1))()
+    flags = (_lib.CHECK_FINITE if finite else 0) | (_lib.CHECK_DIVERGENCE if divergence else 0)
+    st = _lib.load().nadmm_register_checked(dims_of(shp), ctypes.byref(p), ctypes.c_uint32(flags), _ptr(fixed),
+                                            _ptr(moving), _ptr(init_disp), _ptr(disp), _ptr(warped), div,
+                                            _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    msg = _lib.load().nadmm_last_error().decode(errors="replace") if st else ""
+    if st not in (0, 5, 6):
+        _lib.check("nadmm_register_checked", st)
+    return {"disp": disp, "warped": warped, "status": int(st), "message": msg, "diverged": list(div)[:outer]}
+
+
 def register_threshold(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
                        outer: int, iters: int, tol_admm: float, tol_warp: float, data_term: int = 2,
                        eps: float = 1e-8, ws: torch.Tensor | None = None) -> dict:

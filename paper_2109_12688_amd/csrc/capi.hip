@@ -270,6 +270,11 @@ struct StopRule {
   double* warp_change;   // host, nullable: outer - 1 measured changes
   int32_t* iters_run;    // host, nullable: ADMM iterations of each warping
   int outer_run;
+  // divergence guard (thresholds off): |s^1 - s^0|^2 into slot 0 and
+  // |s^{K-1} - s^{K-2}|^2 into slot 1 of every warping with K >= 3
+  bool guard;
+  int32_t* diverged;     // host, nullable: 1 for each warping whose guard tripped
+  int n_diverged;
 };
 
 // Enqueue the partial sums of |a - b|^2 and |a|^2 over n floats, written by
@@ -279,6 +284,19 @@ nadmm_status change_enqueue(const float* a, const float* b, size_t n, StopRule* 
   stop->nb[slot] = change_blocks(n);
   HIP_TRY(launch_change_partials(a, b, n, stop->host_dev + (size_t)kSlotDoubles * slot, st));
   HIP_TRY(hipEventRecord(stop->ev[slot], st));
+  return NADMM_OK;
+}
+
+// Wait for slot `slot` and add its partials in block order: |a - b|^2 and |a|^2.
+nadmm_status change_sums(StopRule* stop, int slot, double& d, double& n) {
+  HIP_TRY(hipEventSynchronize(stop->ev[slot]));
+  const double* part = stop->host + (size_t)kSlotDoubles * slot;
+  d = 0.0;
+  n = 0.0;
+  for (int j = 0; j < stop->nb[slot]; ++j) {
+    d += part[2 * j];
+    n += part[2 * j + 1];
+  }
   return NADMM_OK;
 }
 
@@ -360,6 +378,8 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     cur = prev;
     prev = tmp;
     if (stop && stop->iters_run) stop->iters_run[warping] = k + 1;
+    if (stop && stop->guard && p->iters >= 3 && (k == 1 || k == p->iters - 1))
+      CHECK(change_enqueue(cur, prev, 3 * (size_t)g.V * batch, stop, k == 1 ? 0 : 1, st));
     if (stop && stop->tol_admm >= 0) {
       // check iteration k (not the last: it ends the loop anyway), then read
       // the check of iteration k - 1, enqueued one iteration ago
@@ -463,6 +483,14 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
     a.vel_out = velocities ? velocities + (size_t)c * 3 * V : nullptr;
     HIP_TRY(timed(KK_PASS_C_COMPOSE, st, [&] { return launch_pass_c(g, pl.x, tb, kBf16 ? kComposeBf16 : kCompose, a, st, batch); }));
     if (stop) stop->outer_run = c + 1;
+    if (stop && stop->guard && p->iters >= 3) {  // read while the composition runs
+      double d0, d1, n0, n1;
+      CHECK(change_sums(stop, 0, d0, n0));
+      CHECK(change_sums(stop, 1, d1, n1));
+      const bool div = !isfinite(d1) || d1 > d0;
+      if (stop->diverged) stop->diverged[c] = div ? 1 : 0;
+      stop->n_diverged += div ? 1 : 0;
+    }
     if (stop && stop->tol_warp >= 0 && c >= 1 && !last) {
       double ch;
       bool below;
@@ -668,6 +696,8 @@ const char* nadmm_status_string(nadmm_status s) {
     case NADMM_ERR_UNSUPPORTED_SIZE: return "NADMM_ERR_UNSUPPORTED_SIZE";
     case NADMM_ERR_WORKSPACE: return "NADMM_ERR_WORKSPACE";
     case NADMM_ERR_HIP: return "NADMM_ERR_HIP";
+    case NADMM_ERR_NONFINITE: return "NADMM_ERR_NONFINITE";
+    case NADMM_ERR_DIVERGED: return "NADMM_ERR_DIVERGED";
   }
   return "NADMM_ERR_UNKNOWN";
 }
@@ -720,6 +750,60 @@ nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, doubl
                       stream, 1, &stop));
   if (outer_run) *outer_run = stop.outer_run;
   HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_register_checked(nadmm_dims d, const nadmm_params* p, uint32_t flags,
+                                    const float* fixed, const float* moving, const float* init_disp,
+                                    float* disp, float* warped, int32_t* diverged, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
+  CHECK(check_dims(d));
+  CHECK(check_params(p, true));
+  if (flags & ~(uint32_t)(NADMM_CHECK_FINITE | NADMM_CHECK_DIVERGENCE))
+    return fail(NADMM_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  CHECK(check_ws(d, workspace, workspace_bytes));
+  CHECK(check_ptr(fixed, "fixed", false));
+  CHECK(check_ptr(moving, "moving", false));
+  CHECK(check_ptr(init_disp, "init_disp", true));
+  CHECK(check_ptr(disp, "disp", false));
+  CHECK(check_ptr(warped, "warped", true));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StopRule stop{};
+  CheckHost res{st};
+  CHECK(res.init(stop));
+  stop.tol_admm = -1.0;
+  stop.tol_warp = -1.0;
+  stop.guard = (flags & NADMM_CHECK_DIVERGENCE) != 0;
+  stop.diverged = diverged;
+  for (int i = 0; diverged && i < p->outer; ++i) diverged[i] = 0;
+  CHECK(register_impl(d, p, fixed, moving, init_disp, disp, warped, nullptr, workspace, workspace_bytes,
+                      stream, 1, &stop));
+  int64_t bad = 0;
+  if (flags & NADMM_CHECK_FINITE) {
+    // counted on the device into the workspace's Jacobian partials, copied
+    // into the pinned read-back slots
+    const Layout L = layout(d);
+    int64_t* cnt = at<int64_t>(workspace, L.jac);
+    const size_t V = (size_t)d.nx * d.ny * d.nz;
+    HIP_TRY(launch_count_nonfinite(disp, 3 * V, cnt, st));
+    HIP_TRY(hipMemcpyAsync(stop.host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (warped) {
+      HIP_TRY(launch_count_nonfinite(warped, V, cnt + 1, st));
+      HIP_TRY(hipMemcpyAsync(stop.host + 1, cnt + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (flags & NADMM_CHECK_FINITE) {
+    int64_t c0 = 0, c1 = 0;
+    memcpy(&c0, stop.host, sizeof(int64_t));
+    if (warped) memcpy(&c1, stop.host + 1, sizeof(int64_t));
+    bad = c0 + c1;
+  }
+  if (bad > 0)
+    return fail(NADMM_ERR_NONFINITE, "%lld non-finite values in the outputs", (long long)bad);
+  if (stop.n_diverged > 0)
+    return fail(NADMM_ERR_DIVERGED, "the ADMM iteration diverged in %d of %d warpings (last fixed-point "
+                "residual above the first)", stop.n_diverged, p->outer);
   return NADMM_OK;
 }
 

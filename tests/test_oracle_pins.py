@@ -513,6 +513,37 @@ def test_p15_divergence_is_visible_in_residuals():
     assert p2[-1] < 1e-8 * p2[0]
 
 
+def test_p15b_divergence_guard():
+    """The guard (no rule in the paper; the reading: after K >= 3 iterations
+    the last fixed-point residual |s^{K-1} - s^{K-2}| exceeds the first
+    |s^1 - s^0|) recomputed from the recorded iterates, s^k = w^k + b^k: set
+    in the divergent regime of P15, clear in its safe regime and for K < 3."""
+    rng = np.random.default_rng(15)
+    J = rng.choice([-1.0, 1.0], size=(3, 4, 4, 4)) / math.sqrt(3)
+    r = rng.uniform(-0.5, 0.5, size=(4, 4, 4))
+
+    def from_history(res):
+        s = [h["w"] + h["b"] for h in res.history]
+        first = np.sum((s[1] - s[0]) ** 2)
+        last = np.sum((s[-1] - s[-2]) ** 2)
+        return bool(not np.isfinite(last) or last > first)
+
+    with np.errstate(all="ignore"):
+        bad = O.admm(J, r, 10.0, 0.1, 1, 60, history=True)
+    assert bad.diverged and from_history(bad)
+    good = O.admm(0.3 * J, r, 0.5, 0.1, 1, 60, history=True)
+    assert not good.diverged and not from_history(good)
+    for k in (1, 2):
+        with np.errstate(all="ignore"):
+            assert not O.admm(J, r, 10.0, 0.1, 1, k).diverged
+    # registration: one flag per warping
+    d = (8, 6, 4)
+    f = synth.random_volume(d, seed=150).astype(np.float64)
+    m = synth.random_volume(d, seed=151).astype(np.float64)
+    reg = O.register(f, m, 0.01, 0.1, 2, 2, 6)
+    assert reg.diverged == [False, False]
+
+
 # ---------------------------------------------------------------------------
 # P16-P19: the adjoint of one warping (reverse mode through Eq. (5), (6))
 # ---------------------------------------------------------------------------
