@@ -275,9 +275,9 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
     wsb = {d: api.workspace_batch((d[2], d[1], d[0]), len(idx)) for d, idx in groups.items()}
     streams = {d: torch.cuda.Stream() for d in groups}
     bouts = {}
-    tiles = {"x".join(map(str, d)): api.autotune((d[2], d[1], d[0]), w["lam"], w["theta"], w["order"],
-                                                  batch=len(idx), ws=wsb[d])
-             for d, idx in groups.items()}
+    for d, idx in groups.items():
+        api.autotune((d[2], d[1], d[0]), w["lam"], w["theta"], w["order"], batch=len(idx), ws=wsb[d])
+    tiles = {"x".join(map(str, d)): api.tuned_shapes((d[2], d[1], d[0])) for d in groups}
 
     def batched():
         cur = torch.cuda.current_stream()
@@ -360,7 +360,7 @@ def batch_vs_plain(api, torch, synth, pairs, reps=2):
             "pairs_per_s_mixed": round(1000.0 * len(specs) / t_mixed, 2),
             "mixed_vs_one_by_one": round(t_plain / t_mixed, 4),
             "mixed_vs_per_size_streams": round(t_batch / t_mixed, 4),
-            "tile_rows": tiles,
+            "tuned_shapes": tiles,
             "bit_identical": bool(same), "mixed_bit_identical": bool(same_mixed)}
 
 
@@ -694,7 +694,8 @@ def main():
     del src, dst
 
     tile_rows = api.autotune(shp, w["lam"], w["theta"], w["order"], ws=ws)
-    log(f"x-line tile: {tile_rows} rows per workgroup")
+    shapes = api.tuned_shapes(shp)
+    log(f"tuned shapes: {shapes}")
     log("warmup")
     for _ in range(args.warmup):
         step()
@@ -774,7 +775,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "dims_xyz": list(w["dims"]), "outer": w["outer"],
                    "iters": w["iters"], "order": w["order"], "lambda": w["lam"], "theta": w["theta"],
-                   "parallelism": "single-gpu", "tile_rows": tile_rows},
+                   "parallelism": "single-gpu", "tuned_shapes": shapes},
         "roofline": roofline,
         "rooflines": rooflines,
         "kernels": kernels,

@@ -290,18 +290,29 @@ nadmm_status nadmm_register_pyramid_threshold(nadmm_dims d, const nadmm_params* 
                                               void* workspace, size_t workspace_bytes,
                                               void* stream);
 
-/* Tile autotuner: times the fused x-line pass of the iteration for every
- * admissible number of y rows per workgroup (even divisors of ny up to 32
- * that fit the kernels' per-thread bounds), `reps` = 20 launches each
- * between HIP events on `stream` (the call waits for them), and keeps the
- * fastest for all later calls with these dims in this process (a
- * process-wide table; tuning while other threads run the same dims changes
- * only their speed).  Results of every entry point are bit for bit the same
- * for any choice.  `workspace` (nadmm_workspace_size_batch(d, batch) bytes)
- * is scratch; the chosen rows go to host *rows (may be NULL).  Not for use
- * inside stream capture. */
+/* Tile autotuner.  Times, with HIP events on `stream` (`reps` = 20 launches
+ * each; the call waits for them), every admissible choice of three launch
+ * shapes and keeps the fastest of each for all later calls with these dims
+ * in this process (process-wide tables; tuning while other threads run the
+ * same dims changes only their speed):
+ *   - y rows per workgroup of the x-line passes (even divisors of ny up to
+ *     32 within the kernels' per-thread bounds), on the fused pass of the
+ *     iteration;
+ *   - y rows per workgroup of the composition pass (the same range), timed
+ *     with a previous displacement of half a voxel everywhere;
+ *   - wavefronts per y-z plane workgroup, from what the plane's transform
+ *     teams need up to 16 (planes that fit one workgroup).
+ * Results of every entry point are bit for bit the same for any choice.
+ * `workspace` (nadmm_workspace_size_batch(d, batch) bytes) is scratch; the
+ * chosen x-line rows go to host *rows (may be NULL).  Not for use inside
+ * stream capture. */
 nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, void* workspace,
                             size_t workspace_bytes, void* stream, int32_t* rows);
+
+/* The launch shapes in use for these dims (host shapes[3]): x-line rows,
+ * composition-pass rows, threads per y-z plane workgroup (0 when the planes
+ * take the three-launch path). */
+nadmm_status nadmm_tuned_shapes(nadmm_dims d, int32_t* shapes);
 
 /* Gradient of one warping's image match (the differentiated hot path):
  *   L = sum_x (I1(x + w(x)) - I0(x))^2,

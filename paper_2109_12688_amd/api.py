@@ -388,6 +388,13 @@ def autotune(vol_shape, lam: float, theta: float, order: int, batch: int = 1,
     return int(rows.value)
 
 
+def tuned_shapes(vol_shape) -> dict:
+    """Launch shapes in use for these sizes (nadmm_tuned_shapes)."""
+    out = (ctypes.c_int32 * 3)()
+    _lib.call("nadmm_tuned_shapes", dims_of(vol_shape), out)
+    return {"xline_rows": out[0], "compose_rows": out[1], "plane_threads": out[2]}
+
+
 def admm(J: torch.Tensor, r: torch.Tensor, lam: float, theta: float, order: int, iters: int,
          data_term: int = 2, eps: float = 1e-8, ws: torch.Tensor | None = None):
     """``iters`` ADMM iterations from zero for a given J, r.  Returns (w, b, v)."""

@@ -970,11 +970,75 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
       best_ms = ms;
     }
   }
+  xline_rows_set(g, best);  // 0 (nothing timed) restores the default
+  // Times `launch` (reps launches after two untimed ones) into *ms.
+  auto time_it = [&](auto&& launch, float* ms) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    return e;
+  };
+  // the composition pass's rows, on the same zero state with a previous
+  // displacement of half a voxel everywhere (every sample between grid
+  // points, the taps of neighbouring voxels neighbouring in memory, as for a
+  // smooth deformation)
+  if (err == hipSuccess) err = launch_fill(at<float>(workspace, L.u), 0.5f, 3 * B * V, st);
+  PassCArgs ac{};
+  ac.X = at<float2>(workspace, L.X);
+  ac.u_old = at<float>(workspace, L.u);
+  ac.img = at<float>(workspace, L.r);
+  ac.out = at<float>(workspace, L.s1);
+  ac.iw_out = at<float>(workspace, L.iw);
+  int best_c = 0;
+  float best_c_ms = 0.f;
+  for (int rows = 2; rows <= 32 && err == hipSuccess; rows += 2) {
+    if (!xline_rows_fit(g, rows, xline_threads_rows(g, rows))) continue;
+    xline_rows_compose_set(g, rows);
+    float ms = 0.f;
+    err = time_it([&] { return launch_pass_c(g, pl.x, tb, kCompose, ac, st, batch); }, &ms);
+    if (err == hipSuccess && (best_c == 0 || ms < best_c_ms)) {
+      best_c = rows;
+      best_c_ms = ms;
+    }
+  }
+  xline_rows_compose_set(g, best_c);
+  // wavefronts of a y-z plane workgroup, from what its team plans need to 16
+  // (one-launch planes only)
+  int best_w = 0;
+  float best_w_ms = 0.f;
+  if (plane_fits(g)) {
+    for (int w = plane_waves_needed(g); w <= 16 && err == hipSuccess; ++w) {
+      plane_waves_set(g, w);
+      float ms = 0.f;
+      err = time_it([&] {
+        return launch_pass_b(g, tb, at<float2>(workspace, L.X), (float)p->lambda, (float)p->theta, p->order, st,
+                             batch);
+      }, &ms);
+      if (err == hipSuccess && (best_w == 0 || ms < best_w_ms)) {
+        best_w = w;
+        best_w_ms = ms;
+      }
+    }
+  }
+  plane_waves_set(g, best_w);
   (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  xline_rows_set(g, best);  // 0 (nothing timed) restores the default
   if (err != hipSuccess) return fail(NADMM_ERR_HIP, "autotune: %s", hipGetErrorString(err));
   if (rows_out) *rows_out = xline_rows(g);
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_tuned_shapes(nadmm_dims d, int32_t* shapes) {
+  CHECK(check_dims(d));
+  if (!shapes) return fail(NADMM_ERR_INVALID_ARG, "shapes is NULL");
+  const Geo g = geo(d);
+  shapes[0] = xline_rows(g);
+  shapes[1] = xline_rows_compose(g);
+  shapes[2] = plane_fits(g) ? plane_threads_tuned(g) : 0;
   return NADMM_OK;
 }
 

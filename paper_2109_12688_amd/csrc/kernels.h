@@ -18,6 +18,18 @@ struct Geo {
 int xline_rows(const Geo& g);
 int xline_rows_default(int ny);
 void xline_rows_set(const Geo& g, int rows);
+// Rows of the composition pass (tuned separately; else xline_rows), and
+// the wavefronts of a y-z plane workgroup (0 restores the default: what the
+// team plans need).  Results do not depend on either.
+int xline_rows_compose(const Geo& g);
+void xline_rows_compose_set(const Geo& g, int rows);
+void plane_waves_set(const Geo& g, int waves);
+int plane_waves_needed(const Geo& g);
+int plane_threads_tuned(const Geo& g);  // threads of a y-z plane workgroup
+// Threads of an x-line workgroup of `rows` rows, and whether those rows fit
+// the x-line kernels' per-thread bounds at `threads` threads.
+int xline_threads_rows(const Geo& g, int rows);
+bool xline_rows_fit(const Geo& g, int rows, int threads);
 // Threads of the x-line passes and of the y-z plane pass for these sizes.
 int xline_threads(const Geo& g);
 int plane_threads(const Geo& g);

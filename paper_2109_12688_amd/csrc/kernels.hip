@@ -78,6 +78,30 @@ void xline_rows_set(const Geo& g, int rows) {
     g_rows.erase(std::make_tuple(g.nx, g.ny, g.nz));
 }
 
+// The other tuned shapes, per sizes (0 or absent: the default): rows of the
+// composition pass (else those of the other x-line passes) and wavefronts of
+// a y-z plane workgroup (at least what the plane's team plans need).
+static std::map<std::tuple<int, int, int>, int> g_rows_compose, g_plane_waves;
+
+static int tuned(const std::map<std::tuple<int, int, int>, int>& t, const Geo& g) {
+  std::lock_guard<std::mutex> lk(g_rows_mu);
+  auto it = t.find(std::make_tuple(g.nx, g.ny, g.nz));
+  return it != t.end() ? it->second : 0;
+}
+static void tune_set(std::map<std::tuple<int, int, int>, int>& t, const Geo& g, int v) {
+  std::lock_guard<std::mutex> lk(g_rows_mu);
+  if (v > 0)
+    t[std::make_tuple(g.nx, g.ny, g.nz)] = v;
+  else
+    t.erase(std::make_tuple(g.nx, g.ny, g.nz));
+}
+int xline_rows_compose(const Geo& g) {
+  const int r = tuned(g_rows_compose, g);
+  return r > 0 ? r : xline_rows(g);
+}
+void xline_rows_compose_set(const Geo& g, int rows) { tune_set(g_rows_compose, g, rows); }
+void plane_waves_set(const Geo& g, int waves) { tune_set(g_plane_waves, g, waves); }
+
 static int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
 // dynamic LDS of pass B for row stride rs: twiddles, symbol tables, plane
@@ -86,7 +110,7 @@ size_t plane_lds_bytes(const Geo& g, int rs) {
          sizeof(float2) * (size_t)g.nz * rs;
 }
 
-static int xline_threads_rows(const Geo& g, int rows) {
+int xline_threads_rows(const Geo& g, int rows) {
   const int elems = 3 * (rows / 2) * g.nx;
   int t = round_up((elems + 7) / 8, 64);
   if (t > 1024) t = 1024;
@@ -96,7 +120,7 @@ static int xline_threads_rows(const Geo& g, int rows) {
 int xline_threads(const Geo& g) { return xline_threads_rows(g, xline_rows(g)); }
 
 // The x-line bounds of launch_shape_ok for `rows` rows and `xt` threads.
-static bool xline_rows_fit(const Geo& g, int rows, int xt) {
+bool xline_rows_fit(const Geo& g, int rows, int xt) {
   return g.ny % rows == 0 && rows % 2 == 0 && 3 * (rows / 2) * g.nx <= kEpt * xt &&
          3 * rows * (g.nx / 4) <= kXItems * xt && rows * (g.nx / 4) <= 2 * xt && 3 * rows * g.nx < 65536;
 }
@@ -188,15 +212,22 @@ static int lane_budget(int nlines) {
 TeamPlan plane_plan_y(const Geo& g) { return make_team_plan(g.ny, lane_budget(g.nz)); }
 TeamPlan plane_plan_z(const Geo& g) { return make_team_plan(g.nz, lane_budget(g.ny)); }
 
-static int plane_team_threads(const Geo& g) {
+int plane_waves_needed(const Geo& g) {
   const TeamPlan py = plane_plan_y(g), pz = plane_plan_z(g);
   const int wy = (g.nz + 64 / py.L - 1) / (64 / py.L);
   const int wz = (g.ny + 64 / pz.L - 1) / (64 / pz.L);
   int w = wy > wz ? wy : wz;
   if (w > 16) w = 16;
   if (w < 1) w = 1;
-  return 64 * w;
+  return w;
 }
+// Threads of a y-z plane workgroup: the tuned wavefronts, never fewer than
+// the team plans need (more only add wavefronts that share the work).
+static int plane_team_threads(const Geo& g) {
+  const int need = plane_waves_needed(g), t = tuned(g_plane_waves, g);
+  return 64 * (t > need && t <= 16 ? t : need);
+}
+int plane_threads_tuned(const Geo& g) { return plane_team_threads(g); }
 
 static bool split_shape_ok(const Geo& g);
 
@@ -1538,10 +1569,11 @@ __global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int
 
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
                          const PassCArgs& a, hipStream_t st, int batch) {
-  const int yb = xline_rows(g);
-  const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads(g));
-  const size_t lds = pass_a_lds(g);
-  const XDivs xd = make_xdivs(g);
+  // the composition pass has rows of its own (tuned separately)
+  const int yb = (mode == kCompose || mode == kComposeBf16) ? xline_rows_compose(g) : xline_rows(g);
+  const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads_rows(g, yb));
+  const size_t lds = pass_a_lds_rows(g, yb);
+  const XDivs xd = make_xdivs_rows(g, yb);
   const int ls = xline_stride(g.nx);
 #define NADMM_PASS_C(M, N) \
   hipLaunchKernelGGL((k_pass_c<M, N>), grid, block, lds, st, g, px, xd, ls, t.twx, a)

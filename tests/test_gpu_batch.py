@@ -62,6 +62,10 @@ def test_autotune_keeps_results(api):
     before = api.register(f, m, *args)
     rows = api.autotune(f.shape, 0.01, 0.1, 2)
     assert rows > 0 and d[1] % rows == 0 and rows % 2 == 0
+    t = api.tuned_shapes(f.shape)
+    assert t["xline_rows"] == rows
+    assert d[1] % t["compose_rows"] == 0 and t["compose_rows"] % 2 == 0
+    assert t["plane_threads"] % 64 == 0 and 64 <= t["plane_threads"] <= 1024
     after = api.register(f, m, *args)
     assert torch.equal(before["disp"], after["disp"])
     assert torch.equal(before["warped"], after["warped"])
