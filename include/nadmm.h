@@ -99,8 +99,11 @@ const char* nadmm_status_string(nadmm_status s);
 const char* nadmm_last_error(void);
 
 /* Size in bytes (written to host *bytes) of the workspace that every entry
- * point below accepts for these dimensions.  `p` may be NULL (the size does
- * not depend on the parameters).  About 14 float32 values per voxel. */
+ * point below accepts for these dimensions (the fields of the Sec. 2 scheme
+ * and of the Sec. 3 iteration: r, the warped source, the two iteration
+ * states, the half spectrum of the Eq. (6) w-step, a displacement, the
+ * Jacobian partials and the transform tables).  `p` may be NULL (the size
+ * does not depend on the parameters).  About 14 float32 values per voxel. */
 nadmm_status nadmm_workspace_size(nadmm_dims d, const nadmm_params* p, size_t* bytes);
 
 /* Full registration: the iterative scheme of Sec. 2 with the
@@ -326,7 +329,9 @@ nadmm_status nadmm_tuned_shapes(nadmm_dims d, int32_t* shapes);
  * iteration states are stored every `checkpoint` (1..30) iterations and
  * recomputed in between.  The image adjoint of the final warp is a
  * scatter-add with float atomics, so d_moving may differ in the last bits
- * between runs.  Workspace: nadmm_workspace_size_grad bytes. */
+ * between runs.  d_moving and d_lambda may both be NULL: then only the loss
+ * is computed (the forward iterations, no reverse pass), the same value as
+ * with them.  Workspace: nadmm_workspace_size_grad bytes. */
 nadmm_status nadmm_workspace_size_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpoint,
                                        size_t* bytes);
 nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpoint,
@@ -364,9 +369,12 @@ nadmm_status nadmm_warp(nadmm_dims d, const float* img, const float* disp, const
 nadmm_status nadmm_compose(nadmm_dims d, const float* u, const float* v, float* out,
                            void* stream);
 
-/* Scaling and squaring of a stationary velocity field: u = vel / 2^steps,
- * then `steps` self-compositions u <- u + u(x + u(x)).  0 <= steps <= 30.
- * out must not alias vel. */
+/* Scaling and squaring of a stationary velocity field (the exponential map
+ * of the diffeomorphic registration framework the paper builds on, Sec. 1,
+ * and of the velocity-field baselines it compares with, Sec. 4): u = vel /
+ * 2^steps, then `steps` self-compositions u <- u + u(x + u(x)), each the
+ * periodic trilinear composition of Eq. (1).  0 <= steps <= 30.  out must
+ * not alias vel. */
 nadmm_status nadmm_expmap(nadmm_dims d, const float* vel, int32_t steps, float* out,
                           void* workspace, size_t workspace_bytes, void* stream);
 

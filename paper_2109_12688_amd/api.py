@@ -286,10 +286,11 @@ def workspace_grad(vol_shape, lam: float, theta: float, order: int, iters: int, 
 
 
 def ssd_grad(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float, order: int,
-             iters: int, checkpoint: int = 5, ws: torch.Tensor | None = None):
+             iters: int, checkpoint: int = 5, ws: torch.Tensor | None = None, loss_only: bool = False):
     """Loss, dL/dmoving and dL/dlambda of one warping's image match
     L = sum (moving(x + w(x)) - fixed(x))^2 (see nadmm_ssd_grad).  Returns
-    (loss, d_moving, d_lambda) with loss and d_lambda float64 0-d tensors."""
+    (loss, d_moving, d_lambda) with loss and d_lambda float64 0-d tensors
+    (loss_only: (loss, None, None), no reverse pass)."""
     _check(fixed, "fixed")
     shp = tuple(fixed.shape)
     _check(moving, "moving", shp)
@@ -297,8 +298,8 @@ def ssd_grad(fixed: torch.Tensor, moving: torch.Tensor, lam: float, theta: float
         ws = workspace_grad(shp, lam, theta, order, iters, checkpoint, fixed.device)
     _check(ws, "workspace", dtype=torch.uint8)
     loss = torch.empty((), dtype=torch.float64, device=fixed.device)
-    dlam = torch.empty((), dtype=torch.float64, device=fixed.device)
-    dmov = torch.empty_like(moving)
+    dlam = None if loss_only else torch.empty((), dtype=torch.float64, device=fixed.device)
+    dmov = None if loss_only else torch.empty_like(moving)
     p = params(lam, theta, order, 1, iters)
     _lib.call("nadmm_ssd_grad", dims_of(shp), ctypes.byref(p), ctypes.c_int32(checkpoint), _ptr(fixed),
               _ptr(moving), _ptr(loss), _ptr(dmov), _ptr(dlam), _ptr(ws), ctypes.c_size_t(ws.numel()),

@@ -3,10 +3,13 @@
 `one_warping_ssd(moving, lam, fixed, theta, order, iters, checkpoint)` is
 L = sum (moving(x + w(x)) - fixed(x))^2 with w the velocity of one warping
 (`iters` unrolled Nesterov-ADMM iterations from u = 0), differentiable with
-respect to `moving` and `lam` (a 0-d tensor).  The forward pass calls the
-library's gradient entry point, which runs the iterations with checkpoints
-every `checkpoint` iterations and the reverse pass in its own kernels; the
-backward pass only scales the stored gradients by the incoming gradient.
+respect to `moving` and `lam` (a 0-d tensor, best on the CPU: the library
+takes lambda as a host value, so a GPU tensor costs a synchronisation).
+When a gradient is required the forward pass calls the library's gradient
+entry point, which runs the iterations with checkpoints every `checkpoint`
+iterations and the reverse pass in its own kernels, and the backward pass
+only scales the stored gradients by the incoming gradient; otherwise the
+forward pass computes the loss alone (no reverse pass).
 """
 from __future__ import annotations
 
@@ -18,9 +21,14 @@ from . import api
 class _OneWarpingSSD(torch.autograd.Function):
     @staticmethod
     def forward(ctx, moving, lam, fixed, theta, order, iters, checkpoint):
-        loss, dmov, dlam = api.ssd_grad(fixed.contiguous(), moving.contiguous(), float(lam.item()),
-                                        theta, order, iters, checkpoint)
-        ctx.save_for_backward(dmov, dlam)
+        # lambda is a host parameter of the library: a CPU tensor costs nothing,
+        # a GPU tensor one synchronisation
+        lam_f = float(lam.item()) if isinstance(lam, torch.Tensor) else float(lam)
+        need = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
+        loss, dmov, dlam = api.ssd_grad(fixed.contiguous(), moving.contiguous(), lam_f, theta, order, iters,
+                                        checkpoint, loss_only=not need)
+        if need:
+            ctx.save_for_backward(dmov, dlam)
         return loss
 
     @staticmethod

@@ -1175,8 +1175,11 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
   CHECK(check_grad_args(p, checkpoint));
   CHECK(check_ptr(fixed, "fixed", false));
   CHECK(check_ptr(moving, "moving", false));
-  CHECK(check_ptr(d_moving, "d_moving", false));
-  if (!loss || !d_lambda) return fail(NADMM_ERR_INVALID_ARG, "loss and d_lambda must not be NULL");
+  // both gradients, or neither (the loss alone: no reverse pass)
+  const bool grads = d_moving || d_lambda;
+  CHECK(check_ptr(d_moving, "d_moving", !grads));
+  if (!loss || (grads && !d_lambda))
+    return fail(NADMM_ERR_INVALID_ARG, "loss must not be NULL, and d_moving and d_lambda are both set or both NULL");
   CHECK(check_ptr(workspace, "workspace", false));
   const GradLayout L = grad_layout(d, p->iters, checkpoint);
   if (workspace_bytes < L.total)
@@ -1233,6 +1236,12 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
   }
   float* s_last = fwd_slot(K - 1);
   HIP_TRY(spectral_apply(g, pl, tb, p, s_last, nullptr, 0.0f, X, w, st));
+  if (!grads) {  // the loss alone: the same warp and residual as the adjoint kernel's
+    HIP_TRY(launch_warp(g, moving, w, tmp, st));
+    HIP_TRY(launch_grad_resid(g, tmp, fixed, nullptr, resid, nullptr, theta, (float)p->eps, 2, st));
+    HIP_TRY(launch_dot(V, resid, resid, 1.0, false, part, loss, st));
+    return NADMM_OK;
+  }
 
   // loss, the image adjoint of the final warp, dL/dw
   HIP_TRY(launch_fill(d_moving, 0.0f, V, st));

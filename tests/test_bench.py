@@ -37,3 +37,17 @@ def test_traffic_record_matches_sources_and_bytes(kernel):
     assert rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"] == rec["traffic_bytes_per_launch"]
     # the copy probe moved one vector field in and one out
     assert rec["copy_bytes"] == 3 * V * 4
+
+
+def test_input_generation_leaves_no_process(tmp_path):
+    """The benchmark's input pool (run before the GPU is touched) leaves no
+    child process behind."""
+    code = (
+        "import sys, argparse; sys.path.insert(0, %r)\n"
+        "import bench, psutil\n"
+        "a = argparse.Namespace(workload='blobs32', no_bf16=True, no_grad=True, no_batch=True)\n"
+        "bench.generate_inputs(a)\n"
+        "print(len(psutil.Process().children(recursive=True)))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "0"

@@ -90,6 +90,12 @@ def test_autograd_function(api):
     assert loss.item() == l2.item()
     assert np.abs(host(gm) - 3.0 * host(dm)).max() <= 1e-6 * np.abs(host(dm)).max()
     assert abs(gl.item() - 3.0 * dl.item()) <= 1e-12 * abs(dl.item())
+    # no gradient required: the loss alone (no reverse pass), the same value
+    with torch.no_grad():
+        l3 = one_warping_ssd(gpu(m), 0.01, gpu(f), 0.1, 2, 6, 3)
+    l4, n1, n2 = api.ssd_grad(gpu(f), gpu(m), 0.01, 0.1, 2, 6, checkpoint=3, loss_only=True)
+    assert n1 is None and n2 is None
+    assert l3.item() == l2.item() and l4.item() == l2.item()
 
 
 def test_blobs96_finite_differences_and_oracle(api):
