@@ -89,11 +89,17 @@ def parse():
                     help="skip the paper's three-level schedule on the same pair")
     ap.add_argument("--no-dram-check", action="store_true",
                     help="skip the 8-copy batched registration (the iteration beyond the Infinity Cache)")
+    ap.add_argument("--shapes", type=lambda t: [int(v) for v in t.split(",")], default=None,
+                    metavar="ROWS,COMPOSE_ROWS,PLANE_THREADS",
+                    help="pin the launch shapes of the timed workload instead of autotuning them")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a device-to-device copy of known size first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the traffic record from two rocprofv3 --pmc counter files and exit")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.shapes is not None and len(args.shapes) != 3:
+        ap.error("--shapes takes three integers: ROWS,COMPOSE_ROWS,PLANE_THREADS")
+    return args
 
 
 def sources_digest() -> str:
@@ -108,10 +114,13 @@ def copy_probe_bytes(V: int) -> int:
     return 3 * V * 4  # one vector field, read once and written once
 
 
-def traffic_record(fetch_csv, write_csv, workload, kernel):
+def traffic_record(fetch_csv, write_csv, workload, kernel, shapes=None):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of `kernel`, each scaled by
-    what the same counter reads for the copy probe of known size."""
+    what the same counter reads for the copy probe of known size.  shapes:
+    the launch shapes the profiled run was pinned to (--shapes), recorded
+    with the workgroup size its dispatches had."""
     import numpy as np
+    wg = {}
 
     def per_dispatch(path, counter):
         sums = {}
@@ -123,6 +132,7 @@ def traffic_record(fetch_csv, write_csv, workload, kernel):
                         if name.startswith(pre)), None)
             if key is None:
                 continue
+            wg[key] = int(r["Workgroup_Size"])
             d = sums.setdefault(key, {})
             d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
         # median over dispatches: the probe's copy kernel also serves a few
@@ -141,20 +151,29 @@ def traffic_record(fetch_csv, write_csv, workload, kernel):
     rec["read_bytes_per_launch"] = round(1024.0 * f[kernel] * sf)
     rec["write_bytes_per_launch"] = round(1024.0 * w[kernel] * sw)
     rec["traffic_bytes_per_launch"] = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    rec["workgroup_size"] = wg.get(kernel)
+    if shapes:
+        rec["shapes"] = {"xline_rows": shapes[0], "compose_rows": shapes[1], "plane_threads": shapes[2]}
     return rec
 
 
-def stored_traffic(workload, kernel):
+def stored_traffic(workload, kernel, shapes=None):
     """HBM bytes per launch from the committed counter record, or None when
-    there is none or the kernel sources changed since it was taken."""
+    there is none, the kernel sources changed since it was taken, or the
+    record was taken at other x-line rows than `shapes` (tuned_shapes) has
+    (the rows set which halo rows the fused pass re-reads)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         if line.startswith("record: "):
             rec = json.loads(line[len("record: "):])
-            if rec.get("sources_sha256") == sources_digest() and rec.get("kernel") == kernel:
-                return rec
+            if rec.get("sources_sha256") != sources_digest() or rec.get("kernel") != kernel:
+                return None
+            rs = rec.get("shapes")
+            if shapes and rs and kernel == "pass_ca_iter" and rs["xline_rows"] != shapes["xline_rows"]:
+                return None
+            return rec
     return None
 
 
@@ -614,17 +633,18 @@ def iteration_rooflines(api, step, shp, w, ws, workload, reps=200):
     its nominal FFT work against the non-packed FP32 vector rate."""
     import numpy as np
     V = int(np.prod(shp))
+    shapes = api.tuned_shapes(shp)
     out = {}
     for kind in ("admm_iteration", "pass_ca_iter", "pass_b_yz_solve"):
         step()
         avg_s = api.profile_replay(shp, kind, reps, w["lam"], w["theta"], w["order"], ws) / 1e3
         if kind == "admm_iteration":
             bpl = ITER_FLOOR_BYTES_PER_VOXEL * V
-            tr = [stored_traffic(workload, k) for k in ("pass_ca_iter", "pass_b_yz_solve")]
+            tr = [stored_traffic(workload, k, shapes) for k in ("pass_ca_iter", "pass_b_yz_solve")]
             traffic = (sum(t["traffic_bytes_per_launch"] for t in tr) if all(tr) else None)
         else:
             bpl = BYTES_PER_VOXEL[kind] * V
-            t = stored_traffic(workload, kind)
+            t = stored_traffic(workload, kind, shapes)
             traffic = t["traffic_bytes_per_launch"] if t else None
         ach = bpl / avg_s / 1e9
         r = {"kernel": kind, "avg_us": round(avg_s * 1e6, 3), "bytes_per_launch": bpl, "bound": "hbm",
@@ -647,7 +667,7 @@ def main():
     if args.traffic_from:
         for kind in ("pass_ca_iter", "pass_b_yz_solve"):
             print("record: " + json.dumps(traffic_record(args.traffic_from[0], args.traffic_from[1],
-                                                           args.workload, kind)))
+                                                           args.workload, kind, args.shapes)))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): registrations would shard "
@@ -695,7 +715,11 @@ def main():
     copy_gbs = 2 * copy_probe_bytes(V) / (c0.elapsed_time(c1) / ncopy * 1e-3) / 1e9
     del src, dst
 
-    tile_rows = api.autotune(shp, w["lam"], w["theta"], w["order"], ws=ws)
+    if args.shapes:
+        # pinned shapes (profiled runs: a profiler distorts the autotuner's timings)
+        api.set_shapes(shp, *args.shapes)
+    else:
+        api.autotune(shp, w["lam"], w["theta"], w["order"], ws=ws)
     shapes = api.tuned_shapes(shp)
     log(f"tuned shapes: {shapes}")
     log("warmup")

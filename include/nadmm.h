@@ -308,7 +308,8 @@ nadmm_status nadmm_register_pyramid_threshold(nadmm_dims d, const nadmm_params* 
  * Results of every entry point are bit for bit the same for any choice.
  * `workspace` (nadmm_workspace_size_batch(d, batch) bytes) is scratch; the
  * chosen x-line rows go to host *rows (may be NULL).  Not for use inside
- * stream capture. */
+ * stream capture.  With the environment variable NADMM_AUTOTUNE_LOG set,
+ * every candidate's mean time per launch is written to stderr. */
 nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, void* workspace,
                             size_t workspace_bytes, void* stream, int32_t* rows);
 
@@ -316,6 +317,18 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
  * composition-pass rows, threads per y-z plane workgroup (0 when the planes
  * take the three-launch path). */
 nadmm_status nadmm_tuned_shapes(nadmm_dims d, int32_t* shapes);
+
+/* Sets the three launch shapes of nadmm_tuned_shapes for these dims without
+ * timing anything (host shapes[3]: x-line rows, composition-pass rows,
+ * threads per y-z plane workgroup; 0 restores a shape's default), e.g. the
+ * values an earlier nadmm_autotune chose, so that runs (and profiles) use
+ * the same shapes.  Rows must be even divisors of ny up to 32 within the
+ * kernels' per-thread bounds; plane threads a multiple of 64 from what the
+ * plane's transform teams need to 1024, and only for dims whose planes fit
+ * one workgroup.  Invalid values: NADMM_ERR_INVALID_ARG and nothing
+ * changes.  The same process-wide tables as nadmm_autotune; results are bit
+ * for bit the same for any valid shapes. */
+nadmm_status nadmm_set_shapes(nadmm_dims d, const int32_t* shapes);
 
 /* Gradient of one warping's image match (the differentiated hot path):
  *   L = sum_x (I1(x + w(x)) - I0(x))^2,

@@ -71,6 +71,7 @@ _SIGS = {
     "nadmm_autotune": ([Dims, ctypes.c_int32, ctypes.POINTER(Params), _P, ctypes.c_size_t, _P,
                         ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "nadmm_tuned_shapes": ([Dims, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "nadmm_set_shapes": ([Dims, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "nadmm_workspace_size_pyramid": ([Dims, ctypes.POINTER(Pyramid), ctypes.POINTER(ctypes.c_size_t)],
                                      ctypes.c_int),
     "nadmm_register_pyramid": ([Dims, ctypes.POINTER(Params), ctypes.POINTER(Pyramid), _P, _P, _P, _P, _P,

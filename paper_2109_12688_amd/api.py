@@ -396,6 +396,13 @@ def tuned_shapes(vol_shape) -> dict:
     return {"xline_rows": out[0], "compose_rows": out[1], "plane_threads": out[2]}
 
 
+def set_shapes(vol_shape, xline_rows: int = 0, compose_rows: int = 0, plane_threads: int = 0) -> None:
+    """Pins the launch shapes for these sizes without timing (nadmm_set_shapes;
+    0 restores a shape's default)."""
+    arr = (ctypes.c_int32 * 3)(xline_rows, compose_rows, plane_threads)
+    _lib.call("nadmm_set_shapes", dims_of(vol_shape), arr)
+
+
 def admm(J: torch.Tensor, r: torch.Tensor, lam: float, theta: float, order: int, iters: int,
          data_term: int = 2, eps: float = 1e-8, ws: torch.Tensor | None = None):
     """``iters`` ADMM iterations from zero for a given J, r.  Returns (w, b, v)."""

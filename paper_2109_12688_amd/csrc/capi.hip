@@ -7,6 +7,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <type_traits>
@@ -952,6 +953,13 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
   int best = 0;
   float best_ms = 0.f;
   const int reps = 20;
+  // NADMM_AUTOTUNE_LOG set: every candidate's time per launch on stderr
+  const bool log = getenv("NADMM_AUTOTUNE_LOG") != nullptr;
+  auto note = [&](const char* what, int value, float ms) {
+    if (log)
+      fprintf(stderr, "nadmm_autotune %dx%dx%d batch %d: %s %d: %.3f us per launch\n", d.nx, d.ny, d.nz, batch,
+              what, value, 1000.f * ms / reps);
+  };
   for (int rows = 2; rows <= 32 && err == hipSuccess; rows += 2) {
     if (g.ny % rows) continue;
     xline_rows_set(g, rows);
@@ -965,6 +973,7 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.f;
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess) note("fused x-line pass rows", rows, ms);
     if (err == hipSuccess && (best == 0 || ms < best_ms)) {
       best = rows;
       best_ms = ms;
@@ -1000,6 +1009,7 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
     xline_rows_compose_set(g, rows);
     float ms = 0.f;
     err = time_it([&] { return launch_pass_c(g, pl.x, tb, kCompose, ac, st, batch); }, &ms);
+    if (err == hipSuccess) note("composition pass rows", rows, ms);
     if (err == hipSuccess && (best_c == 0 || ms < best_c_ms)) {
       best_c = rows;
       best_c_ms = ms;
@@ -1018,6 +1028,7 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
         return launch_pass_b(g, tb, at<float2>(workspace, L.X), (float)p->lambda, (float)p->theta, p->order, st,
                              batch);
       }, &ms);
+      if (err == hipSuccess) note("y-z pass wavefronts", w, ms);
       if (err == hipSuccess && (best_w == 0 || ms < best_w_ms)) {
         best_w = w;
         best_w_ms = ms;
@@ -1039,6 +1050,40 @@ nadmm_status nadmm_tuned_shapes(nadmm_dims d, int32_t* shapes) {
   shapes[0] = xline_rows(g);
   shapes[1] = xline_rows_compose(g);
   shapes[2] = plane_fits(g) ? plane_threads_tuned(g) : 0;
+  return NADMM_OK;
+}
+
+nadmm_status nadmm_set_shapes(nadmm_dims d, const int32_t* shapes) {
+  CHECK(check_dims(d));
+  if (!shapes) return fail(NADMM_ERR_INVALID_ARG, "shapes is NULL");
+  const Geo g = geo(d);
+  const int rows = shapes[0], crows = shapes[1], threads = shapes[2];
+  if (rows < 0 || crows < 0 || threads < 0) return fail(NADMM_ERR_INVALID_ARG, "shapes must be >= 0");
+  auto rows_ok = [&](int r) {
+    return r <= 32 && r % 2 == 0 && g.ny % r == 0 && xline_rows_fit(g, r, xline_threads_rows(g, r));
+  };
+  if (rows > 0 && !rows_ok(rows))
+    return fail(NADMM_ERR_INVALID_ARG, "x-line rows %d: not an even divisor of ny = %d up to 32 that fits", rows,
+                d.ny);
+  if (crows > 0 && !rows_ok(crows))
+    return fail(NADMM_ERR_INVALID_ARG, "composition rows %d: not an even divisor of ny = %d up to 32 that fits",
+                crows, d.ny);
+  if (threads > 0) {
+    if (!plane_fits(g))
+      return fail(NADMM_ERR_INVALID_ARG, "plane threads: the y-z planes of these dims take the three-launch path");
+    const int w = threads / 64;
+    if (threads % 64 || w < plane_waves_needed(g) || w > 16)
+      return fail(NADMM_ERR_INVALID_ARG, "plane threads %d: a multiple of 64 from %d to 1024", threads,
+                  64 * plane_waves_needed(g));
+  }
+  const int old_rows = xline_rows_tuned(g);
+  xline_rows_set(g, rows);
+  if (!launch_shape_ok(g)) {
+    xline_rows_set(g, old_rows);
+    return fail(NADMM_ERR_INVALID_ARG, "x-line rows %d do not fit these dims", rows);
+  }
+  xline_rows_compose_set(g, crows);
+  plane_waves_set(g, threads / 64);
   return NADMM_OK;
 }
 

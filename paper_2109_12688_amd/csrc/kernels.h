@@ -18,6 +18,7 @@ struct Geo {
 int xline_rows(const Geo& g);
 int xline_rows_default(int ny);
 void xline_rows_set(const Geo& g, int rows);
+int xline_rows_tuned(const Geo& g);  // the value set for these sizes, 0 if none
 // Rows of the composition pass (tuned separately; else xline_rows), and
 // the wavefronts of a y-z plane workgroup (0 restores the default: what the
 // team plans need).  Results do not depend on either.

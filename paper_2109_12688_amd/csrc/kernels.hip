@@ -70,6 +70,12 @@ int xline_rows(const Geo& g) {
   return it != g_rows.end() ? it->second : xline_rows_default(g.ny);
 }
 
+int xline_rows_tuned(const Geo& g) {
+  std::lock_guard<std::mutex> lk(g_rows_mu);
+  auto it = g_rows.find(std::make_tuple(g.nx, g.ny, g.nz));
+  return it != g_rows.end() ? it->second : 0;
+}
+
 void xline_rows_set(const Geo& g, int rows) {
   std::lock_guard<std::mutex> lk(g_rows_mu);
   if (rows > 0)
@@ -592,6 +598,17 @@ __device__ __forceinline__ void xline_tile(const Blk& bk, int& by, int& z) {
   by = l - z * nby;
 }
 
+// Run idx of an x-line block (four consecutive x of one row): consecutive
+// runs alternate between the two rows of a pair.  The rows of a pair share
+// one complex LDS line (real and imaginary parts), so the 32 lanes of a half
+// wavefront reading or writing their runs' floats reach all 32 banks (one
+// row per lane would reach only the 16 banks of its parity).
+__device__ __forceinline__ void run_of(int idx, int q4, const XDivs& xd, int& row, int& x4) {
+  const int pr = (int)fdiv((uint32_t)(idx >> 1), xd.q4);
+  x4 = (idx >> 1) - pr * q4;
+  row = 2 * pr + (idx & 1);
+}
+
 // x-line transform of a block: the compile-time plan when NX is one of the
 // specialised lengths, else the host-made plan.
 template <int NX, bool INV>
@@ -668,8 +685,8 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
   for (int it = 0; it < kXItems; ++it) {
     const int idx = threadIdx.x + it * nthr;
     if (idx < items) {
-      const int row = (int)fdiv((uint32_t)idx, xd.q4);
-      const int x4 = idx - row * q4;
+      int row, x4;
+      run_of(idx, q4, xd, row, x4);
       const int c = (int)fdiv((uint32_t)row, xd.yb);
       const int yy = row - c * yb;
       goff[it] = c * g.V + (z * g.ny + y0 + yy) * nx + 4 * x4;
@@ -682,8 +699,8 @@ __global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int
   for (int it = 0; it < kXItems; ++it) {
     const int idx = threadIdx.x + it * nthr;
     if (idx < items) {
-      const int row = (int)fdiv((uint32_t)idx, xd.q4);
-      const int x4 = idx - row * q4;
+      int row, x4;
+      run_of(idx, q4, xd, row, x4);
       const int c = (int)fdiv((uint32_t)row, xd.yb);
       const int yy = row - c * yb;
       float4 t = va[it];
@@ -1260,8 +1277,9 @@ __device__ __forceinline__ void pass_a0_body(const Geo& g, const FftPlan& px, co
   float* bf = reinterpret_cast<float*>(buf);
   const int nitems = yb * q4;
   for (int idx = threadIdx.x; idx < nitems; idx += nthr) {
-    const int yy = (int)fdiv((uint32_t)idx, xd.q4);
-    const int x0 = 4 * (idx - yy * q4);
+    int yy, x4;
+    run_of(idx, q4, xd, yy, x4);
+    const int x0 = 4 * x4;
     const uint32_t go = ((uint32_t)z * g.ny + y0 + yy) * nx + x0;
     float4 J[3];
     run_gradient(g, nx, iw, x0, y0 + yy, z, J);
@@ -1393,7 +1411,8 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
 #pragma unroll
   for (int it = 0; it < MI; ++it) {
     const int idx = threadIdx.x + it * nthr;
-    const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
+    int yy, x4;
+    run_of(idx, q4, xd, yy, x4);
     gi[it] = (z * g.ny + y0 + yy) * nx + 4 * x4;
   }
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
@@ -1425,7 +1444,8 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
   // LDS slots of run it, component c: four consecutive x of one real row
   auto run_slot = [&](int it, int c) {
     const int idx = threadIdx.x + it * nthr;
-    const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
+    int yy, x4;
+    run_of(idx, q4, xd, yy, x4);
     return bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<kXlPadsh>(4 * x4)) + (yy & 1);
   };
   float4 yv[MI][3];
@@ -1454,8 +1474,9 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
     for (int it = 0; it < MI; ++it) {
       const int idx = threadIdx.x + it * nthr;
       if (idx >= nitems) break;
-      const int yy = (int)fdiv((uint32_t)idx, xd.q4);
-      const int x0 = 4 * (idx - yy * q4);
+      int yy, x4;
+      run_of(idx, q4, xd, yy, x4);
+      const int x0 = 4 * x4;
       const int go = (z * g.ny + y0 + yy) * nx + x0;
       float4 s1v[3], s2v[3], jv[3], yr[3];
 #pragma unroll
@@ -1529,7 +1550,8 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
     for (int it = 0; it < MI; ++it) {
       const int idx = threadIdx.x + it * nthr;
       if (idx < nitems) {
-        const int yy = (int)fdiv((uint32_t)idx, xd.q4), x4 = idx - yy * q4;
+        int yy, x4;
+        run_of(idx, q4, xd, yy, x4);
         float4 un[3], iw;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {

@@ -214,3 +214,28 @@ def test_pyramid_argument_checks(lib):
     assert lib.nadmm_workspace_size_pyramid(Dims(24, 24, 24), ctypes.byref(py), ctypes.byref(n)) == 2
     py.levels = 5
     assert lib.nadmm_workspace_size_pyramid(Dims(64, 64, 64), ctypes.byref(py), ctypes.byref(n)) == 1
+
+
+def test_set_shapes_pins_and_validates(lib):
+    """nadmm_set_shapes (host tables only): valid shapes read back through
+    nadmm_tuned_shapes, invalid ones are rejected and change nothing, and 0
+    restores the defaults."""
+    d = Dims(128, 128, 96)
+    out = (ctypes.c_int32 * 3)()
+    assert lib.nadmm_tuned_shapes(d, out) == 0
+    default = list(out)
+    assert lib.nadmm_set_shapes(d, (ctypes.c_int32 * 3)(16, 4, 1024)) == 0
+    assert lib.nadmm_tuned_shapes(d, out) == 0 and list(out) == [16, 4, 1024]
+    for bad in ([6, 4, 1024], [34, 4, 1024], [16, 3, 1024], [16, 4, 1000], [16, 4, 2048], [16, 4, 64],
+                [-2, 4, 1024]):
+        assert lib.nadmm_set_shapes(d, (ctypes.c_int32 * 3)(*bad)) == 1, bad
+        assert lib.nadmm_tuned_shapes(d, out) == 0 and list(out) == [16, 4, 1024], bad
+    assert "shape" in lib.nadmm_last_error().decode() or "rows" in lib.nadmm_last_error().decode()
+    assert lib.nadmm_set_shapes(d, None) == 1
+    # planes of 192 x 128 take the three-launch path: no plane threads to set
+    big = Dims(192, 192, 128)
+    assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(0, 0, 256)) == 1
+    assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(8, 8, 0)) == 0
+    assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(0, 0, 0)) == 0
+    assert lib.nadmm_set_shapes(d, (ctypes.c_int32 * 3)(0, 0, 0)) == 0
+    assert lib.nadmm_tuned_shapes(d, out) == 0 and list(out) == default

@@ -71,6 +71,25 @@ def test_autotune_keeps_results(api):
     assert torch.equal(before["warped"], after["warped"])
 
 
+def test_pinned_shapes_keep_results(api):
+    """Shapes pinned with nadmm_set_shapes (non-default rows and plane
+    threads) give the same registration bit for bit."""
+    d = (32, 24, 16)
+    f = gpu(synth.random_volume(d, seed=112, smooth_kmax=3))
+    m = gpu(synth.random_volume(d, seed=113, smooth_kmax=3))
+    args = (0.01, 0.1, 2, 2, 5)
+    api.set_shapes(f.shape)
+    before = api.register(f, m, *args)
+    for shapes in ((2, 4, 0), (8, 2, 0), (4, 8, 1024)):
+        api.set_shapes(f.shape, *shapes)
+        t = api.tuned_shapes(f.shape)
+        assert t["xline_rows"] == shapes[0] and t["compose_rows"] == shapes[1]
+        after = api.register(f, m, *args)
+        assert torch.equal(before["disp"], after["disp"]), shapes
+        assert torch.equal(before["warped"], after["warped"]), shapes
+    api.set_shapes(f.shape)
+
+
 def test_graph_replay_matches_eager(api):
     """A registration captured in a graph: several replays, with eager work
     and synchronisations between them, each equal to the eager result."""
