@@ -16,7 +16,7 @@ struct Geo {
 // the value set for these sizes by xline_rows_set (the autotuner; 0 clears
 // it), else a default.  Results do not depend on it.
 int xline_rows(const Geo& g);
-int xline_rows_default(int ny);
+int xline_rows_default(const Geo& g);
 void xline_rows_set(const Geo& g, int rows);
 int xline_rows_tuned(const Geo& g);  // the value set for these sizes, 0 if none
 // Rows of the composition pass (tuned separately; else xline_rows), and
@@ -67,6 +67,10 @@ bool plane_fits(const Geo& g);
 bool launch_shape_ok(const Geo& g);
 // Per-thread item bounds the batched loads are compiled for (checked on the host).
 constexpr int kXItems = 4;   // float4 groups per thread in the x-line passes
+// threads of an x-line workgroup at most: the launch bound the x-line kernels
+// are compiled for (a launch with more threads is outside what the compiler
+// assumed for them)
+constexpr int kXlMaxThreads = 768;
 constexpr int kPItems = 8;   // float4 (two complex) per thread in the plane pass
 
 // Transform tables, generated once per call into the workspace in float64

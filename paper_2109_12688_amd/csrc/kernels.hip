@@ -54,20 +54,23 @@ static inline int xline_stride(int nx) { return xl_pad_host(nx); }
 // ---------------------------------------------------------------------------
 // Rows per x-line workgroup: the tuned value for these sizes when one was
 // set (xline_rows_set, from the autotuner), else the largest even divisor of
-// ny up to kXlMaxRows.
+// ny up to kXlMaxRows and up to 1024 / nx (192 threads for the three
+// components' 8-point shares; measured at nx = 192: 4 rows 52-54 us, 8 rows
+// 63-69 us for the fused pass of a 192 x 192 x 128 volume).
 static std::mutex g_rows_mu;
 static std::map<std::tuple<int, int, int>, int> g_rows;
 
-int xline_rows_default(int ny) {
-  for (int yb = kXlMaxRows; yb >= 2; yb -= 2)
-    if (ny % yb == 0) return yb;
+int xline_rows_default(const Geo& g) {
+  const int cap = 1024 / g.nx < kXlMaxRows ? 1024 / g.nx : kXlMaxRows;
+  for (int yb = cap & ~1; yb >= 2; yb -= 2)
+    if (g.ny % yb == 0) return yb;
   return 2;
 }
 
 int xline_rows(const Geo& g) {
   std::lock_guard<std::mutex> lk(g_rows_mu);
   auto it = g_rows.find(std::make_tuple(g.nx, g.ny, g.nz));
-  return it != g_rows.end() ? it->second : xline_rows_default(g.ny);
+  return it != g_rows.end() ? it->second : xline_rows_default(g);
 }
 
 int xline_rows_tuned(const Geo& g) {
@@ -119,7 +122,7 @@ size_t plane_lds_bytes(const Geo& g, int rs) {
 int xline_threads_rows(const Geo& g, int rows) {
   const int elems = 3 * (rows / 2) * g.nx;
   int t = round_up((elems + 7) / 8, 64);
-  if (t > 1024) t = 1024;
+  if (t > kXlMaxThreads) t = kXlMaxThreads;
   if (t < 64) t = 64;
   return t;
 }
@@ -127,7 +130,7 @@ int xline_threads(const Geo& g) { return xline_threads_rows(g, xline_rows(g)); }
 
 // The x-line bounds of launch_shape_ok for `rows` rows and `xt` threads.
 bool xline_rows_fit(const Geo& g, int rows, int xt) {
-  return g.ny % rows == 0 && rows % 2 == 0 && 3 * (rows / 2) * g.nx <= kEpt * xt &&
+  return xt <= kXlMaxThreads && g.ny % rows == 0 && rows % 2 == 0 && 3 * (rows / 2) * g.nx <= kEpt * xt &&
          3 * rows * (g.nx / 4) <= kXItems * xt && rows * (g.nx / 4) <= 2 * xt && 3 * rows * g.nx < 65536;
 }
 
@@ -247,6 +250,7 @@ bool launch_shape_ok(const Geo& g) {
   const bool point_c = yb * (g.nx / 4) <= 2 * xt;             // pass C float4 runs
   (void)pt;
   const bool div_x = 3 * yb * g.nx < 65536;  // FastDiv range of the x-line index maps
+  const bool bound_x = xt <= kXlMaxThreads;   // the x-line kernels' launch bound
   bool pass_b;
   if (plane_fits(g)) {
     const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
@@ -254,7 +258,7 @@ bool launch_shape_ok(const Geo& g) {
   } else {
     pass_b = split_shape_ok(g);
   }
-  return fft_a && load_a && point_c && pass_b && div_x;
+  return fft_a && load_a && point_c && pass_b && div_x && bound_x;
 }
 
 static XDivs make_xdivs_rows(const Geo& g, int yb) {
@@ -658,7 +662,7 @@ __device__ __forceinline__ void store_half_spectrum(const Geo& g, const XDivs& x
 }
 
 template <int NX>
-__global__ void __launch_bounds__(768) k_pass_a(Geo g, FftPlan px, XDivs xd, int ls,
+__global__ void __launch_bounds__(kXlMaxThreads) k_pass_a(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx,
                                                 const float* __restrict__ s1,
                                                 const float* __restrict__ s2, float gamma,
@@ -1313,7 +1317,7 @@ __device__ __forceinline__ void pass_a0_body(const Geo& g, const FftPlan& px, co
 }
 
 template <int NX, typename T>
-__global__ void __launch_bounds__(768) k_pass_a0(Geo g, FftPlan px, XDivs xd, int ls,
+__global__ void __launch_bounds__(kXlMaxThreads) k_pass_a0(Geo g, FftPlan px, XDivs xd, int ls,
                                                  const float2* __restrict__ twx,
                                                  const float* __restrict__ iw,
                                                  const T* __restrict__ ref, float* __restrict__ r_out,
@@ -1584,7 +1588,7 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
 }
 
 template <int MODE, int NX>
-__global__ void __launch_bounds__(768) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
+__global__ void __launch_bounds__(kXlMaxThreads) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx, PassCArgs a) {
   pass_c_body<MODE, NX>(g, px, xd, ls, twx, a, Blk::of_block());
 }
@@ -1833,7 +1837,7 @@ __global__ void k_mixed_tables(const MixedDesc md) {
   tables_body(mc.g, mc.tab, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(768) k_mixed_pass_a0(const MixedDesc md, const float* __restrict__ iw,
+__global__ void __launch_bounds__(kXlMaxThreads) k_mixed_pass_a0(const MixedDesc md, const float* __restrict__ iw,
                                                        const float* __restrict__ ref, float* __restrict__ r,
                                                        float* __restrict__ s0, float theta, float eps,
                                                        int data_term, float2* __restrict__ X) {
@@ -1859,7 +1863,7 @@ __global__ void __launch_bounds__(768) k_mixed_pass_a0(const MixedDesc md, const
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(768) k_mixed_pass_c(const MixedDesc md, PassCArgs a) {
+__global__ void __launch_bounds__(kXlMaxThreads) k_mixed_pass_c(const MixedDesc md, PassCArgs a) {
   const MixedTile t = mixed_xline_tile(md);
   const MixedClass& mc = md.c[t.cls];
   const Geo g = mc.g;

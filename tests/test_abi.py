@@ -236,6 +236,12 @@ def test_set_shapes_pins_and_validates(lib):
     big = Dims(192, 192, 128)
     assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(0, 0, 256)) == 1
     assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(8, 8, 0)) == 0
+    # 24 or 32 rows of 192-point lines would need more threads than the x-line
+    # kernels' launch bound of 768: rejected, x-line and composition rows alike
+    for rows in (24, 32):
+        assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(rows, 8, 0)) == 1, rows
+        assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(8, rows, 0)) == 1, rows
+    assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(16, 12, 0)) == 0
     assert lib.nadmm_set_shapes(big, (ctypes.c_int32 * 3)(0, 0, 0)) == 0
     assert lib.nadmm_set_shapes(d, (ctypes.c_int32 * 3)(0, 0, 0)) == 0
     assert lib.nadmm_tuned_shapes(d, out) == 0 and list(out) == default

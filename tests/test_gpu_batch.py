@@ -71,6 +71,21 @@ def test_autotune_keeps_results(api):
     assert torch.equal(before["warped"], after["warped"])
 
 
+def test_autotune_large_lines_stays_within_launch_bound(api):
+    """Autotuning 192-point x lines (planes of 192 x 128 on the three-launch
+    path) considers only rows whose workgroups fit the x-line kernels'
+    768-thread launch bound (24 and 32 rows would need 864 and 1152) and
+    completes; the registration is unchanged by the chosen shapes."""
+    shp = (128, 192, 192)
+    ws = api.workspace(shp)
+    rows = api.autotune(shp, 0.005, 0.1, 3, ws=ws)
+    torch.cuda.synchronize()
+    t = api.tuned_shapes(shp)
+    assert rows == t["xline_rows"] and rows in (2, 4, 6, 8, 12, 16)
+    assert t["compose_rows"] in (2, 4, 6, 8, 12, 16) and t["plane_threads"] == 0
+    api.set_shapes(shp)
+
+
 def test_pinned_shapes_keep_results(api):
     """Shapes pinned with nadmm_set_shapes (non-default rows and plane
     threads) give the same registration bit for bit."""
