@@ -44,6 +44,12 @@
 extern "C" {
 #endif
 
+/* The entry points declared below are the library's only exported symbols
+ * (it is built with hidden visibility for everything else). */
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility push(default)
+#endif
+
 #define NADMM_ABI_VERSION 1
 
 typedef enum {
@@ -449,6 +455,10 @@ int nadmm_profile_read(int max, const char** names, int64_t* counts, double* tot
 nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t kind, int32_t reps,
                                   void* workspace, size_t workspace_bytes, void* stream,
                                   double* avg_ms);
+
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility pop
+#endif
 
 #ifdef __cplusplus
 }

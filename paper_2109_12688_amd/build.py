@@ -25,6 +25,9 @@ HIPCC_FLAGS = [
     "-Wall",
     # packed fp32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # host code: only the C ABI (declared with default visibility in
+    # include/nadmm.h) is exported from the shared library
+    "-Xarch_host", "-fvisibility=hidden",
 ]
 
 
@@ -77,6 +80,8 @@ def build(verbose: bool = False, out: str = LIB, sanitize: bool = False) -> str:
     cmd = [hipcc(), *HIPCC_FLAGS, *(SANITIZE_FLAGS if sanitize else []),
            f'-DNADMM_SOURCE_DIGEST="{sources_digest()}"',
            "-I", os.path.join(ROOT, "include"),
+           # only the C ABI is exported (kernel stubs and C++ helpers stay local)
+           "-Wl,--version-script=" + os.path.join(CSRC, "exports.map"),
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
