@@ -24,6 +24,13 @@
  *           nadmm_autotune (which wait for their own results) only enqueues
  *           work on that stream and returns; results are valid after the
  *           caller synchronises it.
+ * Threads.  Calls are independent of each other: a call reads only its
+ *           arguments, so calls from several host threads on different
+ *           streams with separate buffers and workspaces may overlap.  The
+ *           only shared state is process-wide and guarded: the launch-shape
+ *           tables (nadmm_autotune, nadmm_set_shapes; a change alters speed,
+ *           never results), the timing records of nadmm_profile_*, and the
+ *           scratch array of nadmm_jacobian_noalloc (see there).
  * Errors.   Every entry point validates all arguments before it enqueues
  *           anything, so a call that returns an error has enqueued nothing.
  *           HIP runtime failures return NADMM_ERR_HIP.  nadmm_last_error()

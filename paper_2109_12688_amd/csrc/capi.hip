@@ -10,6 +10,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -65,15 +67,21 @@ struct ProfRecord {
   int kind;
   hipEvent_t start, stop;
 };
-bool g_prof = false;
+// Timing instrumentation: process-wide, safe to use from several threads
+// (the records and the pool of reusable events are guarded by g_prof_mu).
+std::atomic<bool> g_prof{false};
+std::mutex g_prof_mu;
 std::vector<ProfRecord> g_records;
 std::vector<hipEvent_t> g_free_events;
 
 hipEvent_t take_event() {
-  if (!g_free_events.empty()) {
-    hipEvent_t e = g_free_events.back();
-    g_free_events.pop_back();
-    return e;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_free_events.empty()) {
+      hipEvent_t e = g_free_events.back();
+      g_free_events.pop_back();
+      return e;
+    }
   }
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -83,7 +91,7 @@ hipEvent_t take_event() {
 // Runs launch() and, when timing is on, brackets it with events on st.
 template <class F>
 hipError_t timed(int kind, hipStream_t st, F&& launch) {
-  if (!g_prof) return launch();
+  if (!g_prof.load(std::memory_order_relaxed)) return launch();
   ProfRecord r{kind, take_event(), take_event()};
   if (!r.start || !r.stop) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(r.start, st);
@@ -92,6 +100,7 @@ hipError_t timed(int kind, hipStream_t st, F&& launch) {
   if (e != hipSuccess) return e;
   e = hipEventRecord(r.stop, st);
   if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   g_records.push_back(r);
   return hipSuccess;
 }
@@ -1533,7 +1542,7 @@ nadmm_status nadmm_profile_replay(nadmm_dims d, const nadmm_params* p, int32_t k
 }
 
 nadmm_status nadmm_profile_enable(int enable) {
-  g_prof = enable != 0;
+  g_prof.store(enable != 0);
   return NADMM_OK;
 }
 
@@ -1541,7 +1550,12 @@ int nadmm_profile_read(int max, const char** names, int64_t* counts, double* tot
   int64_t cnt[KK_COUNT] = {0};
   double ms[KK_COUNT] = {0};
   int status = KK_COUNT;
-  for (const ProfRecord& r : g_records) {
+  std::vector<ProfRecord> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_records);
+  }
+  for (const ProfRecord& r : recs) {
     float t = 0.f;
     if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) {
       status = -1;
@@ -1549,10 +1563,14 @@ int nadmm_profile_read(int max, const char** names, int64_t* counts, double* tot
       cnt[r.kind] += 1;
       ms[r.kind] += t;
     }
-    g_free_events.push_back(r.start);
-    g_free_events.push_back(r.stop);
   }
-  g_records.clear();
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (const ProfRecord& r : recs) {
+      g_free_events.push_back(r.start);
+      g_free_events.push_back(r.stop);
+    }
+  }
   for (int k = 0; k < KK_COUNT && k < max; ++k) {
     if (names) names[k] = kKindNames[k];
     if (counts) counts[k] = cnt[k];
