@@ -71,7 +71,11 @@ constexpr int kXItems = 4;   // float4 groups per thread in the x-line passes
 // are compiled for (a launch with more threads is outside what the compiler
 // assumed for them)
 constexpr int kXlMaxThreads = 768;
-constexpr int kPItems = 8;   // float4 (two complex) per thread in the plane pass
+// float4 (two complex) per thread and batch in the plane pass's row loads;
+// a wavefront's rows of 128 points arrive in two batches of 4 (measured at
+// 128x128x96: 7.10 ms per registration against 7.16 with one batch of 8,
+// 7.15 with 6, 7.20 with 3 or 2)
+constexpr int kPItems = 4;
 
 // Transform tables, generated once per call into the workspace in float64
 // and rounded once: tw* = exp(-2 pi i k / n), s* = 2 - 2 cos(2 pi k / n)
