@@ -1471,10 +1471,11 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
 #pragma unroll
         for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
   } else if (MODE == kIterFwd || MODE == kIterFwdIw) {
-    // one run at a time keeps the register footprint small (occupancy hides
-    // the latency); out may alias s2, and each run is read and written by
-    // the same thread only
-#pragma unroll 1
+    // the runs one after the other (out may alias s2, so a run's loads stay
+    // behind the previous run's stores; each run is read and written by the
+    // same thread only); unrolled, at the same register count as a loop
+    // (measured at 128x128x96: 18.88 -> 18.76 us)
+#pragma unroll
     for (int it = 0; it < MI; ++it) {
       const int idx = threadIdx.x + it * nthr;
       if (idx >= nitems) break;
