@@ -38,8 +38,9 @@
  * Sizes.    nx must be a multiple of 4 and ny even; every dimension must be 2^a * 3^b with
  *           4 <= n <= 256.  Other sizes return NADMM_ERR_UNSUPPORTED_SIZE.
  *           (y-z spectral planes of up to 16384 points are transformed in
- *           one pass in a compute unit's local memory, larger ones in three
- *           passes; results do not depend on which.)
+ *           one pass in a compute unit's local memory, larger ones as two
+ *           half planes when ny is a multiple of 8 and a half plane fits,
+ *           else in three passes; results agree to rounding.)
  */
 #ifndef NADMM_H
 #define NADMM_H
@@ -328,7 +329,7 @@ nadmm_status nadmm_autotune(nadmm_dims d, int32_t batch, const nadmm_params* p, 
 
 /* The launch shapes in use for these dims (host shapes[3]): x-line rows,
  * composition-pass rows, threads per y-z plane workgroup (0 when the planes
- * take the three-launch path). */
+ * do not fit one workgroup: half planes or three launches). */
 nadmm_status nadmm_tuned_shapes(nadmm_dims d, int32_t* shapes);
 
 /* Sets the three launch shapes of nadmm_tuned_shapes for these dims without

@@ -62,11 +62,22 @@ struct XDivs {
   FastDiv nh;     // nx / 2 (packed half-spectrum length)
   FastDiv lines;  // complex lines per x-line workgroup: 3 * yb / 2
   FastDiv ny, nz;
+  // Rows of a tile: ygrp consecutive rows, or (half-plane y-z pass, yhalf =
+  // ny / 2 > 0) two groups of ygrp = rows / 2 rows yhalf apart; yq = row
+  // pairs per group.
+  int ygrp, yhalf;
+  FastDiv yq;
 };
 XDivs make_xdivs(const Geo& g);
 // True when a y-z plane of the half spectrum fits one workgroup's LDS (pass B
 // in one launch); otherwise pass B runs as three launches (rows, columns, rows).
 bool plane_fits(const Geo& g);
+// True when a y-z plane does not fit one workgroup but its two halves of
+// ny / 2 x nz do: the x-line passes then take a radix-2 step of the y
+// transform (tiles of two row groups ny / 2 apart; the half spectrum stored
+// as two sub-planes per plane, the even and the odd y frequencies) and
+// pass B transforms each sub-plane in one workgroup.
+bool ysplit(const Geo& g);
 // True when every kernel's compile-time per-thread bounds hold for these sizes.
 bool launch_shape_ok(const Geo& g);
 // Per-thread item bounds the batched loads are compiled for (checked on the host).
@@ -127,6 +138,7 @@ struct PassCArgs {
   const uint16_t* img_bf16;  // kComposeBf16: moving image (bfloat16 bit patterns)
   float* iw_out;       // kCompose: optional moving(x + u_new(x))
   float* vel_out;      // kCompose: optional velocity of this warping
+  const float2* twy;   // y twiddles (the radix-2 y step of half-plane sizes)
 };
 
 hipError_t launch_fill(float* p, float value, size_t n, hipStream_t st);

@@ -30,6 +30,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <utility>
 #include <type_traits>
 
 #include "kernels.h"
@@ -61,6 +62,9 @@ static std::mutex g_rows_mu;
 static std::map<std::tuple<int, int, int>, int> g_rows;
 
 int xline_rows_default(const Geo& g) {
+  if (ysplit(g)) {  // two groups of 4 rows (runs of 32 bytes), else of 2
+    return (g.ny / 2) % 4 == 0 ? 8 : 4;
+  }
   const int cap = 1024 / g.nx < kXlMaxRows ? 1024 / g.nx : kXlMaxRows;
   for (int yb = cap & ~1; yb >= 2; yb -= 2)
     if (g.ny % yb == 0) return yb;
@@ -129,8 +133,15 @@ int xline_threads_rows(const Geo& g, int rows) {
 int xline_threads(const Geo& g) { return xline_threads_rows(g, xline_rows(g)); }
 
 // The x-line bounds of launch_shape_ok for `rows` rows and `xt` threads.
+// Half-plane sizes: a tile is two groups of rows / 2 rows, each a whole
+// number of row pairs dividing ny / 2.
+static bool ysplit_rows_ok(const Geo& g, int rows) {
+  return !ysplit(g) || (rows % 4 == 0 && (g.ny / 2) % (rows / 2) == 0);
+}
+
 bool xline_rows_fit(const Geo& g, int rows, int xt) {
-  return xt <= kXlMaxThreads && g.ny % rows == 0 && rows % 2 == 0 && 3 * (rows / 2) * g.nx <= kEpt * xt &&
+  return xt <= kXlMaxThreads && g.ny % rows == 0 && rows % 2 == 0 && ysplit_rows_ok(g, rows) &&
+         3 * (rows / 2) * g.nx <= kEpt * xt &&
          3 * rows * (g.nx / 4) <= kXItems * xt && rows * (g.nx / 4) <= 2 * xt && 3 * rows * g.nx < 65536;
 }
 
@@ -162,7 +173,22 @@ FftPlan make_plan(int n) {
   return p;
 }
 
-TeamPlan make_team_plan(int n, int max_lanes) { return make_team_plan_ce(n, max_lanes); }
+// The host's plan searches are memoised (every y-z pass launch asks for its
+// plans and row stride; the searches cost microseconds of host time).
+TeamPlan make_team_plan(int n, int max_lanes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, TeamPlan> memo;
+  const auto key = std::make_pair(n, max_lanes);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  const TeamPlan p = make_team_plan_ce(n, max_lanes);
+  std::lock_guard<std::mutex> lk(mu);
+  memo[key] = p;
+  return p;
+}
 TeamPlan reverse_team_plan(const TeamPlan& p) { return reverse_team_plan_ce(p); }
 
 // Row stride (complex) of the padded [z][y] plane of pass B: element (z, y)
@@ -209,7 +235,18 @@ constexpr int plane_row_stride_ce(int ny, int nz, const TeamPlan& py, const Team
 }
 
 int plane_row_stride(const Geo& g) {
-  return plane_row_stride_ce(g.ny, g.nz, plane_plan_y(g), plane_plan_z(g));
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int> memo;
+  const auto key = std::make_pair(g.ny, g.nz);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  const int rs = plane_row_stride_ce(g.ny, g.nz, plane_plan_y(g), plane_plan_z(g));
+  std::lock_guard<std::mutex> lk(mu);
+  memo[key] = rs;
+  return rs;
 }
 
 // Lane budget of one line in pass B: a 1024-thread workgroup shared by the
@@ -256,9 +293,9 @@ bool launch_shape_ok(const Geo& g) {
     const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
     pass_b = ty.nstages > 0 && tz.nstages > 0 && g.ny * g.nz < 65536;  // team plans, FastDiv range
   } else {
-    pass_b = split_shape_ok(g);
+    pass_b = ysplit(g) || split_shape_ok(g);
   }
-  return fft_a && load_a && point_c && pass_b && div_x && bound_x;
+  return fft_a && load_a && point_c && pass_b && div_x && bound_x && ysplit_rows_ok(g, yb);
 }
 
 static XDivs make_xdivs_rows(const Geo& g, int yb) {
@@ -270,6 +307,10 @@ static XDivs make_xdivs_rows(const Geo& g, int yb) {
   d.lines = make_fastdiv(3 * (yb / 2));
   d.ny = make_fastdiv(g.ny);
   d.nz = make_fastdiv(g.nz);
+  const bool split = ysplit(g);
+  d.ygrp = split ? yb / 2 : yb;
+  d.yhalf = split ? g.ny / 2 : 0;
+  d.yq = make_fastdiv(split ? yb / 4 : (yb / 2 > 0 ? yb / 2 : 1));
   return d;
 }
 XDivs make_xdivs(const Geo& g) { return make_xdivs_rows(g, xline_rows(g)); }
@@ -629,41 +670,87 @@ __device__ __forceinline__ void x_transform(float2* buf, const float2* tw, const
 // Bins 0 and nx/2 of a real row are real: they go to planes 0 and nx/2 with
 // zero imaginary part.  With the 1 / nx here an x transform followed by the
 // inverse of pass C is the identity.
-template <int NX>
+// Row y of tile row t (0 <= t < rows) of x-line tile by: consecutive rows,
+// or, for half-plane sizes, two groups of ygrp rows ny / 2 apart.
+__device__ __forceinline__ int tile_row(const XDivs& xd, int by, int t) {
+  return by * xd.ygrp + t + (t >= xd.ygrp ? xd.yhalf - xd.ygrp : 0);
+}
+
+template <int NX, bool YS = false>
 __device__ __forceinline__ void store_half_spectrum(const Geo& g, const XDivs& xd, int ls,
                                                     const float2* buf, float2* __restrict__ X,
-                                                    int y0, int z) {
+                                                    const float2* __restrict__ twy, int by, int z) {
   const int nx = NX ? NX : g.nx, nh = nx / 2;
   const int yb2 = (int)xd.yb2.d;
   const int nthr = blockDim.x;
-  const int nout = 3 * nh * yb2;
   const float s1 = 1.0f / (float)nx, sh = 0.5f * s1;
-  for (int idx = threadIdx.x; idx < nout; idx += nthr) {
-    const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
-    const int yp = idx - ck * yb2;
-    const int c = (int)fdiv((uint32_t)ck, xd.nh);
-    const int k = ck - c * nh;
+  // bin k of the two rows of line pair yp, (a.re, a.im, b.re, b.im); for
+  // k = 0 also the Nyquist bin (both real)
+  auto bins = [&](int c, int yp, int k, float4& o, float4& on) {
     const float2* Z = buf + (c * yb2 + yp) * ls;
-    float4 o;
     if (k == 0) {
       const float2 z0 = Z[0], zn = Z[lpad<kXlPadsh>(nh)];
       o = make_float4(z0.x * s1, 0.f, z0.y * s1, 0.f);
-      float2* dn = X + ((size_t)(c * (nh + 1) + nh) * g.nz + z) * g.ny + y0 + 2 * yp;
-      store_wt(reinterpret_cast<float4*>(dn), make_float4(zn.x * s1, 0.f, zn.y * s1, 0.f));
+      on = make_float4(zn.x * s1, 0.f, zn.y * s1, 0.f);
     } else {
       const float2 zk = Z[lpad<kXlPadsh>(k)], zm = Z[lpad<kXlPadsh>(nx - k)];
       // a = (Zk + conj(Zm)) / 2 ; b = -i (Zk - conj(Zm)) / 2
       o = make_float4(sh * (zk.x + zm.x), sh * (zk.y - zm.y), sh * (zk.y + zm.y),
                       -sh * (zk.x - zm.x));
+      on = o;
     }
-    float2* dst = X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y0 + 2 * yp;
-    store_wt(reinterpret_cast<float4*>(dst), o);
+  };
+  if constexpr (!YS) {
+    const int nout = 3 * nh * yb2;
+    for (int idx = threadIdx.x; idx < nout; idx += nthr) {
+      const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
+      const int yp = idx - ck * yb2;
+      const int c = (int)fdiv((uint32_t)ck, xd.nh);
+      const int k = ck - c * nh;
+      const int y = by * xd.ygrp + 2 * yp;
+      float4 o, on;
+      bins(c, yp, k, o, on);
+      if (k == 0)
+        store_wt(reinterpret_cast<float4*>(X + ((size_t)(c * (nh + 1) + nh) * g.nz + z) * g.ny + y), on);
+      store_wt(reinterpret_cast<float4*>(X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y), o);
+    }
+  } else {
+    // First step of the y transform, decimation in frequency by 2 across the
+    // tile's row groups: rows n (A) and n + ny/2 (B) give A + B, stored in
+    // sub-plane 0 (the even y frequencies), and (A - B) W^n, W = exp(-2 pi i
+    // / ny), in sub-plane 1 (the odd ones); sub-plane s of plane (c, k) holds
+    // element (z, n) at s * nz * ny/2 + z * ny/2 + n.
+    const int yq = (int)xd.yq.d, nyh = xd.yhalf;
+    const size_t sub = (size_t)g.nz * nyh;
+    const int nout = 3 * nh * yq;
+    for (int idx = threadIdx.x; idx < nout; idx += nthr) {
+      const int ck = (int)fdiv((uint32_t)idx, xd.yq);
+      const int j = idx - ck * yq;
+      const int c = (int)fdiv((uint32_t)ck, xd.nh);
+      const int k = ck - c * nh;
+      const int n = by * xd.ygrp + 2 * j;
+      const float2 w0 = twy[n], w1 = twy[n + 1];
+      float4 a, an, b, bn;
+      bins(c, j, k, a, an);
+      bins(c, j + yq, k, b, bn);
+      auto put = [&](int plane, const float4& A, const float4& B) {
+        float2* d = X + (size_t)(c * (nh + 1) + plane) * g.nz * g.ny + (size_t)z * nyh + n;
+        store_wt(reinterpret_cast<float4*>(d), make_float4(A.x + B.x, A.y + B.y, A.z + B.z, A.w + B.w));
+        const float ex = A.x - B.x, ey = A.y - B.y, fx = A.z - B.z, fy = A.w - B.w;
+        store_wt(reinterpret_cast<float4*>(d + sub),
+                 make_float4(ex * w0.x - ey * w0.y, ex * w0.y + ey * w0.x, fx * w1.x - fy * w1.y,
+                             fx * w1.y + fy * w1.x));
+      };
+      put(k, a, b);
+      if (k == 0) put(nh, an, bn);
+    }
   }
 }
 
-template <int NX>
+template <int NX, bool YS = false>
 __global__ void __launch_bounds__(kXlMaxThreads) k_pass_a(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx,
+                                                const float2* __restrict__ twy,
                                                 const float* __restrict__ s1,
                                                 const float* __restrict__ s2, float gamma,
                                                 float2* __restrict__ X) {
@@ -677,7 +764,6 @@ __global__ void __launch_bounds__(kXlMaxThreads) k_pass_a(Geo g, FftPlan px, XDi
   float2* buf = lds + nx;
   int by, z;
   xline_tile(Blk::of_block(), by, z);
-  const int y0 = by * yb;
   const int nthr = blockDim.x;
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
 
@@ -693,7 +779,7 @@ __global__ void __launch_bounds__(kXlMaxThreads) k_pass_a(Geo g, FftPlan px, XDi
       run_of(idx, q4, xd, row, x4);
       const int c = (int)fdiv((uint32_t)row, xd.yb);
       const int yy = row - c * yb;
-      goff[it] = c * g.V + (z * g.ny + y0 + yy) * nx + 4 * x4;
+      goff[it] = c * g.V + (z * g.ny + tile_row(xd, by, yy)) * nx + 4 * x4;
       va[it] = *reinterpret_cast<const float4*>(s1 + goff[it]);
       if (s2) vb[it] = *reinterpret_cast<const float4*>(s2 + goff[it]);
     }
@@ -723,7 +809,7 @@ __global__ void __launch_bounds__(kXlMaxThreads) k_pass_a(Geo g, FftPlan px, XDi
   }
   __syncthreads();
   x_transform<NX, false>(buf, tw, px, xd, ls);
-  store_half_spectrum<NX>(g, xd, ls, buf, X, y0, z);
+  store_half_spectrum<NX, YS>(g, xd, ls, buf, X, twy, by, z);
 }
 
 static size_t pass_a_lds_rows(const Geo& g, int yb) {
@@ -739,7 +825,14 @@ hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const
   const XDivs xd = make_xdivs(g);
   const int ls = xline_stride(g.nx);
 #define NADMM_PASS_A(N) \
-  hipLaunchKernelGGL(k_pass_a<N>, grid, block, lds, st, g, px, xd, ls, t.twx, s1, s2, gamma, X)
+  hipLaunchKernelGGL(k_pass_a<N>, grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X)
+  if (ysplit(g)) {
+    if (g.nx == 192)
+      hipLaunchKernelGGL((k_pass_a<192, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X);
+    else
+      hipLaunchKernelGGL((k_pass_a<0, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X);
+    return hipGetLastError();
+  }
   switch (g.nx) {
     case 32: NADMM_PASS_A(32); break;
     case 64: NADMM_PASS_A(64); break;
@@ -792,7 +885,7 @@ struct PlansCT {
   __device__ int lz() const { return PZ.L; }
 
   template <int WHICH, bool INV, int PADSH, int S, int SEND>
-  __device__ static void stages(float2* line, const float2* tw, int tl, int es) {
+  __device__ __forceinline__ static void stages(float2* line, const float2* tw, int tl, int es) {
     if constexpr (S < SEND) {
       constexpr TeamPlan P = WHICH == 0 ? PY : (WHICH == 1 ? PZ : PZI);
       constexpr FftStage st = P.st[S];
@@ -801,11 +894,11 @@ struct PlansCT {
     }
   }
   template <bool INV>
-  __device__ void y_all(float2* line, const float2* tw, int tl) const {
+  __device__ __forceinline__ void y_all(float2* line, const float2* tw, int tl) const {
     stages<0, INV, 4, 0, PY.nstages>(line, tw, tl, 1);
   }
-  __device__ void z_fused(float2* line, const float2* tw, int tl, int es,
-                          const SpectralMult& mult) const {
+  __device__ __forceinline__ void z_fused(float2* line, const float2* tw, int tl, int es,
+                                          const SpectralMult& mult) const {
     stages<1, false, 0, 0, PZ.nstages - 1>(line, tw, tl, es);
     constexpr FftStage sf = PZ.st[PZ.nstages - 1];
     constexpr FftStage si = PZI.st[0];
@@ -816,7 +909,11 @@ struct PlansCT {
 
 // NY = NZ = 0: any size (run-time plans); otherwise the sizes are fixed.
 // DERIV: multiply by d/dlambda of the multiplier (generic kernel only).
-template <int NY, int NZ, bool DERIV = false>
+// SUB: one of the two sub-planes (even or odd y frequencies) of a plane of a
+// half-plane size, bk.y = 2 c + s: the transform runs over ny / 2 (NY when
+// fixed), the plane is addressed and normalised with the full g.ny, and the
+// y twiddles and symbols are the full tables' at 2 q and 2 q + s.
+template <int NY, int NZ, bool DERIV = false, bool SUB = false>
 // tid, nthr: the thread's index within, and the size of, the thread group
 // that transforms this plane (the whole workgroup, or one of several groups
 // sharing it, each with its own LDS at lds); every group of a workgroup
@@ -837,18 +934,19 @@ __device__ __forceinline__ void pass_b_body(const Geo& g, const TeamPlan& py0, c
   Pol pol{};
   if constexpr (NY == 0) pol = PlansRT{plans, plans + 1, plans + 2};
   // plane element (z, y) at z * rs + y + y / 16 (host-chosen rs)
-  const int ny = NY ? NY : g.ny, nz = NZ ? NZ : g.nz, np = g.nx / 2 + 1;
+  const int nyf = g.ny;  // the full y length (addressing, normalisation)
+  const int ny = NY ? NY : (SUB ? nyf / 2 : nyf), nz = NZ ? NZ : g.nz, np = g.nx / 2 + 1;
   const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
   float2* twy = lds;
   float2* twz = twy + ny;
   float* sy = reinterpret_cast<float*>(twz + nz);
   float* sz = sy + ny;
   float2* buf = reinterpret_cast<float2*>(sz + nz + ((ny + nz) & 1));  // keep 8-byte alignment
-  const int p = bk.x, c = bk.y;
-  float2* plane = at_pair(X, spectrum_elems(g), bk.z) + (size_t)(c * np + p) * nz * ny;
+  const int p = bk.x, c = SUB ? bk.y >> 1 : bk.y, ks = SUB ? bk.y & 1 : 0;
+  float2* plane = at_pair(X, spectrum_elems(g), bk.z) + (size_t)(c * np + p) * nz * nyf + (size_t)ks * nz * ny;
   const float4* plane4 = reinterpret_cast<const float4*>(plane);
   // the x transform of pass A already carries 1 / nx of the inverse's 1 / V
-  const float inv_v = 1.0f / (float)(ny * nz);
+  const float inv_v = 1.0f / (float)(nyf * nz);
   const int nlw_y = 64 / (NY ? PlansCT<NY ? NY : 32, NZ ? NZ : 32>::PY.L : py0.L);
   // Compile-time sizes: the host launches at least ceil(nz / nlw_y) and
   // ceil(ny / nlw_z) wavefronts when both are <= 16, so every wavefront owns at
@@ -887,8 +985,8 @@ __device__ __forceinline__ void pass_b_body(const Geo& g, const TeamPlan& py0, c
     float t1 = 0.f;
     const int ti = tid;
     if (ti < ny) {
-      t2 = tg.twy[ti];
-      t1 = tg.sy[ti];
+      t2 = tg.twy[SUB ? 2 * ti : ti];
+      t1 = tg.sy[SUB ? 2 * ti + ks : ti];
     } else if (ti < ny + nz) {
       t2 = tg.twz[ti - ny];
       t1 = tg.sz[ti - ny];
@@ -912,8 +1010,8 @@ __device__ __forceinline__ void pass_b_body(const Geo& g, const TeamPlan& py0, c
     for (int i = ny + nz + tid; i < 2 * (ny + nz); i += nthr) {  // blocks narrower than ny + nz
       const int k = i - (ny + nz);
       if (k < ny) {
-        twy[k] = tg.twy[k];
-        sy[k] = tg.sy[k];
+        twy[k] = tg.twy[SUB ? 2 * k : k];
+        sy[k] = tg.sy[SUB ? 2 * k + ks : k];
       } else {
         twz[k - ny] = tg.twz[k - ny];
         sz[k - ny] = tg.sz[k - ny];
@@ -988,13 +1086,13 @@ __device__ __forceinline__ void pass_b_body(const Geo& g, const TeamPlan& py0, c
   }
 }
 
-template <int NY, int NZ, bool DERIV = false>
+template <int NY, int NZ, bool DERIV = false, bool SUB = false>
 __global__ void __launch_bounds__(1024) k_pass_b(Geo g, TeamPlan py0, TeamPlan pz0, TeamPlan pzi0,
                                                  XDivs xd, int rs_host, Tables tg, float2* __restrict__ X,
                                                  float lambda, float theta, int order) {
   extern __shared__ float2 lds[];
-  pass_b_body<NY, NZ, DERIV>(g, py0, pz0, pzi0, xd, rs_host, tg, X, lambda, theta, order, Blk::of_block(),
-                             threadIdx.x, blockDim.x, lds);
+  pass_b_body<NY, NZ, DERIV, SUB>(g, py0, pz0, pzi0, xd, rs_host, tg, X, lambda, theta, order,
+                                  Blk::of_block(), threadIdx.x, blockDim.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1137,6 +1235,33 @@ bool plane_fits(const Geo& g) {
   return g.ny * g.nz <= 16384 && plane_lds_bytes(g, plane_row_stride(g)) <= (size_t)kMaxLds;
 }
 
+static Geo half_plane_geo(const Geo& g) { return Geo{g.nx, g.ny / 2, g.nz, g.V / 2}; }
+
+static bool ysplit_eval(const Geo& g) {
+  if (g.ny % 8 || plane_fits(g)) return false;
+  const Geo gs = half_plane_geo(g);
+  if (!plane_fits(gs)) return false;
+  const TeamPlan ty = plane_plan_y(gs), tz = plane_plan_z(gs);
+  return ty.nstages > 0 && tz.nstages > 0 && gs.ny * gs.nz < 65536;
+}
+
+// Memoised per sizes: every x-line and plane launch asks, and the answer
+// takes the plane planners' searches.
+bool ysplit(const Geo& g) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int>, bool> memo;
+  const auto key = std::make_tuple(g.nx, g.ny, g.nz);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  const bool v = ysplit_eval(g);
+  std::lock_guard<std::mutex> lk(mu);
+  memo[key] = v;
+  return v;
+}
+
 static bool split_shape_ok(const Geo& g) {
   const SplitShape sh = split_shape(g);
   const FftPlan py = make_plan(g.ny), pz = make_plan(g.nz);
@@ -1189,9 +1314,35 @@ static hipError_t launch_pass_b_split(const Geo& g, const Tables& t, float2* X, 
 
 static size_t pass_b_lds(const Geo& g) { return plane_lds_bytes(g, plane_row_stride(g)); }
 
+// Both sub-planes of every plane of a half-plane size, one workgroup each.
+static hipError_t launch_pass_b_sub(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
+                                    int order, hipStream_t st, int batch, bool deriv) {
+  const Geo gs = half_plane_geo(g);
+  const TeamPlan ty = plane_plan_y(gs), tz = plane_plan_z(gs), tzi = reverse_team_plan(tz);
+  // exactly the wavefronts the sub-plane's team plans need (no tuning)
+  const int waves = plane_waves_needed(gs);
+  const dim3 grid(g.nx / 2 + 1, 6, batch), block(64 * waves);
+  const size_t lds = pass_b_lds(gs);
+  const XDivs xd = make_xdivs_rows(gs, 2);  // only its ny and nz divisors are used
+  const int rs = plane_row_stride(gs);
+  if (!deriv && gs.ny == 96 && gs.nz == 128)  // 192 x 128 planes
+    hipLaunchKernelGGL((k_pass_b<96, 128, false, true>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X,
+                       lambda, theta, order);
+  else if (deriv)
+    hipLaunchKernelGGL((k_pass_b<0, 0, true, true>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X,
+                       lambda, theta, order);
+  else
+    hipLaunchKernelGGL((k_pass_b<0, 0, false, true>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X,
+                       lambda, theta, order);
+  return hipGetLastError();
+}
+
 hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda, float theta,
                          int order, hipStream_t st, int batch, bool deriv) {
-  if (!plane_fits(g)) return launch_pass_b_split(g, t, X, lambda, theta, order, st, batch, deriv);
+  if (!plane_fits(g)) {
+    if (ysplit(g)) return launch_pass_b_sub(g, t, X, lambda, theta, order, st, batch, deriv);
+    return launch_pass_b_split(g, t, X, lambda, theta, order, st, batch, deriv);
+  }
   const TeamPlan ty = plane_plan_y(g), tz = plane_plan_z(g);
   const dim3 grid(g.nx / 2 + 1, 3, batch), block(plane_team_threads(g));
   const size_t lds = pass_b_lds(g);
@@ -1256,9 +1407,10 @@ __device__ __forceinline__ void run_gradient(const Geo& g, int nx, const float* 
 // per run of 4 voxels J = grad I1^w (the differences of k_grad_resid),
 // r = I1^w - I0 and s^0 = the data step from zero, stored (the first
 // iteration reads both) and transformed along x as pass A transforms s^0.
-template <int NX, typename T>
+template <int NX, typename T, bool YS = false>
 __device__ __forceinline__ void pass_a0_body(const Geo& g, const FftPlan& px, const XDivs& xd, int ls,
                                              const float2* __restrict__ twx,
+                                             const float2* __restrict__ twy,
                                              const float* __restrict__ iw,
                                              const T* __restrict__ ref, float* __restrict__ r_out,
                                              float* __restrict__ s0, float theta, float eps,
@@ -1275,7 +1427,6 @@ __device__ __forceinline__ void pass_a0_body(const Geo& g, const FftPlan& px, co
   float2* buf = lds + nx;
   int by, z;
   xline_tile(bk, by, z);
-  const int y0 = by * yb;
   const int nthr = blockDim.x;
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
   float* bf = reinterpret_cast<float*>(buf);
@@ -1284,9 +1435,10 @@ __device__ __forceinline__ void pass_a0_body(const Geo& g, const FftPlan& px, co
     int yy, x4;
     run_of(idx, q4, xd, yy, x4);
     const int x0 = 4 * x4;
-    const uint32_t go = ((uint32_t)z * g.ny + y0 + yy) * nx + x0;
+    const int y = tile_row(xd, by, yy);
+    const uint32_t go = ((uint32_t)z * g.ny + y) * nx + x0;
     float4 J[3];
-    run_gradient(g, nx, iw, x0, y0 + yy, z, J);
+    run_gradient(g, nx, iw, x0, y, z, J);
     const float4 c = ld4_at(iw, go);
     const float4 rv = make_float4(c.x - img_at(ref, go), c.y - img_at(ref, go + 1),
                                   c.z - img_at(ref, go + 2), c.w - img_at(ref, go + 3));
@@ -1313,17 +1465,18 @@ __device__ __forceinline__ void pass_a0_body(const Geo& g, const FftPlan& px, co
   }
   __syncthreads();
   x_transform<NX, false>(buf, tw, px, xd, ls);
-  store_half_spectrum<NX>(g, xd, ls, buf, X, y0, z);
+  store_half_spectrum<NX, YS>(g, xd, ls, buf, X, twy, by, z);
 }
 
-template <int NX, typename T>
+template <int NX, typename T, bool YS = false>
 __global__ void __launch_bounds__(kXlMaxThreads) k_pass_a0(Geo g, FftPlan px, XDivs xd, int ls,
                                                  const float2* __restrict__ twx,
+                                                 const float2* __restrict__ twy,
                                                  const float* __restrict__ iw,
                                                  const T* __restrict__ ref, float* __restrict__ r_out,
                                                  float* __restrict__ s0, float theta, float eps,
                                                  int data_term, float2* __restrict__ X) {
-  pass_a0_body<NX, T>(g, px, xd, ls, twx, iw, ref, r_out, s0, theta, eps, data_term, X, Blk::of_block());
+  pass_a0_body<NX, T, YS>(g, px, xd, ls, twx, twy, iw, ref, r_out, s0, theta, eps, data_term, X, Blk::of_block());
 }
 
 template <typename T>
@@ -1336,8 +1489,17 @@ static hipError_t pass_a0_any(const Geo& g, const FftPlan& px, const Tables& t, 
   const XDivs xd = make_xdivs(g);
   const int ls = xline_stride(g.nx);
 #define NADMM_PASS_A0(N)                                                                     \
-  hipLaunchKernelGGL((k_pass_a0<N, T>), grid, block, lds, st, g, px, xd, ls, t.twx, iw, ref, r, \
+  hipLaunchKernelGGL((k_pass_a0<N, T>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, iw, ref, r, \
                      s0, theta, eps, data_term, X)
+  if (ysplit(g)) {
+    if (g.nx == 192)
+      hipLaunchKernelGGL((k_pass_a0<192, T, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, iw, ref,
+                         r, s0, theta, eps, data_term, X);
+    else
+      hipLaunchKernelGGL((k_pass_a0<0, T, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, iw, ref, r,
+                         s0, theta, eps, data_term, X);
+    return hipGetLastError();
+  }
   switch (g.nx) {
     case 32: NADMM_PASS_A0(32); break;
     case 64: NADMM_PASS_A0(64); break;
@@ -1360,7 +1522,7 @@ hipError_t launch_pass_a0(const Geo& g, const FftPlan& px, const Tables& t, cons
   return pass_a0_any(g, px, t, iw, ref, r, s0, theta, eps, data_term, X, st, batch);
 }
 
-template <int MODE, int NX>
+template <int MODE, int NX, bool YS = false>
 __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, const XDivs& xd, int ls,
                                             const float2* __restrict__ twx, PassCArgs a, const Blk& bk) {
   extern __shared__ float2 lds[];
@@ -1389,23 +1551,50 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
   float2* buf = lds + nx;
   int by, z;
   xline_tile(bk, by, z);
-  const int y0 = by * yb;
 
   // unpack two rows' half spectra into one complex row: Z = Xa + i Xb
   const int nin = 3 * nh * yb2;
   float4 in[kXItems], inn[kXItems];
+  // half-plane sizes: items (c, k, j) over the j-th row pair of each group,
+  // two sub-plane values each (in[it], inn[it]), for k = 0 also the Nyquist
+  // plane's (in[it + KH], inn[it + KH])
+  constexpr int KH = kXItems / 2;
+  const int yq = (int)xd.yq.d, nyh = xd.yhalf;
+  const size_t sub = (size_t)g.nz * nyh;
+  if constexpr (!YS) {
 #pragma unroll
-  for (int it = 0; it < kXItems; ++it) {
-    const int idx = threadIdx.x + it * nthr;
-    if (idx < nin) {
-      const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
-      const int yp = idx - ck * yb2;
-      const int c = (int)fdiv((uint32_t)ck, xd.nh);
-      const int k = ck - c * nh;
-      const float2* src = a.X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + y0 + 2 * yp;
-      in[it] = *reinterpret_cast<const float4*>(src);
-      if (k == 0)  // the Nyquist plane
-        inn[it] = *reinterpret_cast<const float4*>(src + (size_t)nh * g.nz * g.ny);
+    for (int it = 0; it < kXItems; ++it) {
+      const int idx = threadIdx.x + it * nthr;
+      if (idx < nin) {
+        const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
+        const int yp = idx - ck * yb2;
+        const int c = (int)fdiv((uint32_t)ck, xd.nh);
+        const int k = ck - c * nh;
+        const float2* src = a.X + ((size_t)(c * (nh + 1) + k) * g.nz + z) * g.ny + by * xd.ygrp + 2 * yp;
+        in[it] = *reinterpret_cast<const float4*>(src);
+        if (k == 0)  // the Nyquist plane
+          inn[it] = *reinterpret_cast<const float4*>(src + (size_t)nh * g.nz * g.ny);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < KH; ++it) {
+      const int idx = threadIdx.x + it * nthr;
+      if (idx < nin / 2) {
+        const int ck = (int)fdiv((uint32_t)idx, xd.yq);
+        const int jj = idx - ck * yq;
+        const int c = (int)fdiv((uint32_t)ck, xd.nh);
+        const int k = ck - c * nh;
+        const float2* src =
+            a.X + (size_t)(c * (nh + 1) + k) * g.nz * g.ny + (size_t)z * nyh + by * xd.ygrp + 2 * jj;
+        in[it] = *reinterpret_cast<const float4*>(src);
+        inn[it] = *reinterpret_cast<const float4*>(src + sub);
+        if (k == 0) {  // the Nyquist plane
+          const float2* srn = src + (size_t)nh * g.nz * g.ny;
+          in[it + KH] = *reinterpret_cast<const float4*>(srn);
+          inn[it + KH] = *reinterpret_cast<const float4*>(srn + sub);
+        }
+      }
     }
   }
   // float4 runs of 4 voxels along x for the pointwise part
@@ -1417,13 +1606,55 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
     const int idx = threadIdx.x + it * nthr;
     int yy, x4;
     run_of(idx, q4, xd, yy, x4);
-    gi[it] = (z * g.ny + y0 + yy) * nx + 4 * x4;
+    gi[it] = (z * g.ny + tile_row(xd, by, yy)) * nx + 4 * x4;
   }
   for (int i = threadIdx.x; i < nx; i += nthr) tw[i] = twx[i];
+  if constexpr (YS) {
+    // last step of the inverse y transform, decimation in time by 2: rows n
+    // and n + ny/2 are P0 + conj(W^n) P1 and P0 - conj(W^n) P1 of the two
+    // sub-planes' values P0, P1 (the inverse of the forward step in
+    // store_half_spectrum, the factor 1/2 carried by the multiplier's 1/V)
+#pragma unroll
+    for (int it = 0; it < KH; ++it) {
+      const int idx = threadIdx.x + it * nthr;
+      if (idx < nin / 2) {
+        const int ck = (int)fdiv((uint32_t)idx, xd.yq);
+        const int jj = idx - ck * yq;
+        const int c = (int)fdiv((uint32_t)ck, xd.nh);
+        const int k = ck - c * nh;
+        const int n = by * xd.ygrp + 2 * jj;
+        const float2 w0 = a.twy[n], w1 = a.twy[n + 1];
+        // A = P0 + conj(w) P1 and B = P0 - conj(w) P1, per row of the pair
+        auto dit = [&](const float4& P0, const float4& P1, float4& A, float4& B) {
+          const float t0x = w0.x * P1.x + w0.y * P1.y, t0y = w0.x * P1.y - w0.y * P1.x;
+          const float t1x = w1.x * P1.z + w1.y * P1.w, t1y = w1.x * P1.w - w1.y * P1.z;
+          A = make_float4(P0.x + t0x, P0.y + t0y, P0.z + t1x, P0.w + t1y);
+          B = make_float4(P0.x - t0x, P0.y - t0y, P0.z - t1x, P0.w - t1y);
+        };
+        float4 qa, qb;
+        dit(in[it], inn[it], qa, qb);
+        float2* ZA = buf + (c * yb2 + jj) * ls;
+        float2* ZB = buf + (c * yb2 + jj + yq) * ls;
+        if (k == 0) {
+          float4 na, nb;
+          dit(in[it + KH], inn[it + KH], na, nb);
+          ZA[0] = make_float2(qa.x, qa.z);
+          ZA[lpad<kXlPadsh>(nh)] = make_float2(na.x, na.z);
+          ZB[0] = make_float2(qb.x, qb.z);
+          ZB[lpad<kXlPadsh>(nh)] = make_float2(nb.x, nb.z);
+        } else {
+          ZA[lpad<kXlPadsh>(k)] = make_float2(qa.x - qa.w, qa.y + qa.z);
+          ZA[lpad<kXlPadsh>(nx - k)] = make_float2(qa.x + qa.w, qa.z - qa.y);
+          ZB[lpad<kXlPadsh>(k)] = make_float2(qb.x - qb.w, qb.y + qb.z);
+          ZB[lpad<kXlPadsh>(nx - k)] = make_float2(qb.x + qb.w, qb.z - qb.y);
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int it = 0; it < kXItems; ++it) {
     const int idx = threadIdx.x + it * nthr;
-    if (idx < nin) {
+    if (!YS && idx < nin) {
       const int ck = (int)fdiv((uint32_t)idx, xd.yb2);
       const int yp = idx - ck * yb2;
       const int c = (int)fdiv((uint32_t)ck, xd.nh);
@@ -1482,7 +1713,8 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
       int yy, x4;
       run_of(idx, q4, xd, yy, x4);
       const int x0 = 4 * x4;
-      const int go = (z * g.ny + y0 + yy) * nx + x0;
+      const int y = tile_row(xd, by, yy);
+      const int go = (z * g.ny + y) * nx + x0;
       float4 s1v[3], s2v[3], jv[3], yr[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1490,7 +1722,7 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
         s2v[c] = a.s2 ? ld4_at(a.s2 + c * g.V, go) : s1v[c];
         if constexpr (MODE == kIterFwd) jv[c] = ld4_at(a.J + c * g.V, go);
       }
-      if constexpr (MODE == kIterFwdIw) run_gradient(g, nx, a.iw, x0, y0 + yy, z, jv);
+      if constexpr (MODE == kIterFwdIw) run_gradient(g, nx, a.iw, x0, y, z, jv);
       const float4 rv = ld4_at(a.r, go);
       float* slot[3];
 #pragma unroll
@@ -1533,7 +1765,7 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
     }
     __syncthreads();
     x_transform<NX, false>(buf, tw, px, xd, ls);
-    store_half_spectrum<NX>(g, xd, ls, buf, a.X, y0, z);
+    store_half_spectrum<NX, YS>(g, xd, ls, buf, a.X, a.twy, by, z);
   } else if (MODE == kFinalWB) {
 #pragma unroll
     for (int it = 0; it < MI; ++it) {
@@ -1563,7 +1795,7 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
           const float w0 = f4get(yv[it][0], e), w1 = f4get(yv[it][1], e), w2 = f4get(yv[it][2], e);
           float u0 = w0, u1 = w1, u2 = w2;
           if (a.u_old) {  // null: the previous displacement is zero
-            const Tap t = make_tap(4 * x4 + e, y0 + yy, z, w0, w1, w2, g);
+            const Tap t = make_tap(4 * x4 + e, tile_row(xd, by, yy), z, w0, w1, w2, g);
             u0 += sample(a.u_old, t);
             u1 += sample(a.u_old + g.V, t);
             u2 += sample(a.u_old + 2 * g.V, t);
@@ -1572,7 +1804,7 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
           f4set(un[1], e, u1);
           f4set(un[2], e, u2);
           if (a.iw_out) {
-            const Tap t2 = make_tap(4 * x4 + e, y0 + yy, z, u0, u1, u2, g);
+            const Tap t2 = make_tap(4 * x4 + e, tile_row(xd, by, yy), z, u0, u1, u2, g);
             if constexpr (MODE == kComposeBf16) f4set(iw, e, sample(a.img_bf16, t2));
             else f4set(iw, e, sample(a.img, t2));
           }
@@ -1588,10 +1820,10 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
   }
 }
 
-template <int MODE, int NX>
+template <int MODE, int NX, bool YS = false>
 __global__ void __launch_bounds__(kXlMaxThreads) k_pass_c(Geo g, FftPlan px, XDivs xd, int ls,
                                                 const float2* __restrict__ twx, PassCArgs a) {
-  pass_c_body<MODE, NX>(g, px, xd, ls, twx, a, Blk::of_block());
+  pass_c_body<MODE, NX, YS>(g, px, xd, ls, twx, a, Blk::of_block());
 }
 
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
@@ -1602,9 +1834,18 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
   const size_t lds = pass_a_lds_rows(g, yb);
   const XDivs xd = make_xdivs_rows(g, yb);
   const int ls = xline_stride(g.nx);
+  PassCArgs at = a;
+  at.twy = t.twy;
 #define NADMM_PASS_C(M, N) \
-  hipLaunchKernelGGL((k_pass_c<M, N>), grid, block, lds, st, g, px, xd, ls, t.twx, a)
+  hipLaunchKernelGGL((k_pass_c<M, N>), grid, block, lds, st, g, px, xd, ls, t.twx, at)
 #define NADMM_PASS_C_NX(M)                 \
+  if (ysplit(g)) {                         \
+    if (g.nx == 192)                       \
+      hipLaunchKernelGGL((k_pass_c<M, 192, true>), grid, block, lds, st, g, px, xd, ls, t.twx, at); \
+    else                                   \
+      hipLaunchKernelGGL((k_pass_c<M, 0, true>), grid, block, lds, st, g, px, xd, ls, t.twx, at);   \
+    break;                                 \
+  }                                        \
   switch (g.nx) {                          \
     case 32: NADMM_PASS_C(M, 32); break;   \
     case 64: NADMM_PASS_C(M, 64); break;   \
@@ -1855,7 +2096,7 @@ __global__ void __launch_bounds__(kXlMaxThreads) k_mixed_pass_a0(const MixedDesc
   X += mc.os + (int64_t)t.pair * (int64_t)spectrum_elems(g);
 #define NADMM_MIXED_A0(N)                                                                                \
   case N:                                                                                                \
-    pass_a0_body<N, float>(g, px, xd, mc.ls, mc.tab.twx, iw, ref, r, s0, theta, eps, data_term, X, t.bk); \
+    pass_a0_body<N, float>(g, px, xd, mc.ls, mc.tab.twx, mc.tab.twy, iw, ref, r, s0, theta, eps, data_term, X, t.bk); \
     break;
   switch (g.nx) {
     NADMM_MIXED_A0(64) NADMM_MIXED_A0(96) NADMM_MIXED_A0(128) NADMM_MIXED_A0(192)

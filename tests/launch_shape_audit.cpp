@@ -5,7 +5,8 @@
 // offer them), the x-line workgroup must stay within the 768-thread launch
 // bound its kernels are compiled for, within the LDS budget and within the
 // per-thread item counts the kernels unroll; every admissible y-z plane
-// workgroup size must stay within 1024 threads and the LDS budget; the
+// workgroup size must stay within 1024 threads and the LDS budget, for whole
+// planes and for the half planes of sizes whose planes do not fit; the
 // three-launch split shapes within 256 threads.  Exit status 1 and a line
 // per violation otherwise.  Built by tests/test_launch_shapes.py with hipcc;
 // it includes the kernel source for its file-local helpers and runs on the
@@ -73,6 +74,14 @@ int main() {
             if (plane_lds_bytes(g, plane_row_stride(g)) > (size_t)kMaxLds) report("plane LDS", g, w, t);
           }
           plane_waves_set(g, 0);
+        } else if (ysplit(g)) {
+          // half planes: x-line tiles of two row groups, one workgroup per sub-plane
+          const Geo gs = half_plane_geo(g);
+          ++shapes;
+          const int t = plane_threads_tuned(gs), rows = xline_rows(g);
+          if (t > 1024 || t % 64 || t < 64 * plane_waves_needed(gs)) report("half-plane threads", g, 0, t);
+          if (plane_lds_bytes(gs, plane_row_stride(gs)) > (size_t)kMaxLds) report("half-plane LDS", g, 0, t);
+          if (rows % 4 || (ny / 2) % (rows / 2)) report("half-plane x-line rows", g, rows, 0);
         } else {
           const SplitShape sh = split_shape(g);
           ++shapes;

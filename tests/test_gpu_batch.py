@@ -1,6 +1,6 @@
 """GPU parity of the batched registration (nadmm_register_batch): every pair
 of a batch must come out bit for bit as from its own nadmm_register call
-(the batch only adds a grid dimension), at a one-pass and at a split-plane
+(the batch only adds a grid dimension), at a one-pass and at a half-plane
 size; one pair is also checked against the FP64 oracle."""
 import numpy as np
 import pytest
@@ -72,8 +72,8 @@ def test_autotune_keeps_results(api):
 
 
 def test_autotune_large_lines_stays_within_launch_bound(api):
-    """Autotuning 192-point x lines (planes of 192 x 128 on the three-launch
-    path) considers only rows whose workgroups fit the x-line kernels'
+    """Autotuning 192-point x lines (planes of 192 x 128, transformed as half
+    planes) considers only rows whose workgroups fit the x-line kernels'
     768-thread launch bound (24 and 32 rows would need 864 and 1152) and
     completes; the registration is unchanged by the chosen shapes."""
     shp = (128, 192, 192)

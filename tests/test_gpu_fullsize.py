@@ -105,8 +105,9 @@ def test_full_size_fourier_solve_and_admm(api, pair):
 # ---------------------------------------------------------------------------
 # 192x192x128 phantom (n = 3, lambda = 0.005, 10 x 30), images stored as
 # bfloat16 and as float32, in the launch configuration bench.py times for
-# it; its y-z planes (192 x 128) exceed one workgroup's LDS, so pass B runs
-# split.  The final map of this workload folds (the oracle's min det J is
+# it; its y-z planes (192 x 128) exceed one workgroup's LDS, so the x-line
+# passes take a radix-2 y step and pass B transforms half planes of 96 x 128.
+# The final map of this workload folds (the oracle's min det J is
 # about -3 with ~4200 voxels <= 0), and near a fold the composition of
 # warpings amplifies any rounding: the oracle's own steps run in float32
 # (tests/golden/fp32_mirror.py) end up to ~0.1 voxel from the FP64 oracle

@@ -5,8 +5,9 @@ the middle of a larger device allocation whose 64 KB head and tail are
 filled with a sentinel byte; after the call (through the C ABI) the head and
 tail must hold the sentinel, the inputs must be unchanged, and every output
 must equal that of the same call on plain buffers bit for bit.  Sizes: a
-split-plane grid (16 x 192 x 96: y-z planes of 18432 points, three
-launches per Fourier solve), a ragged one-plane grid (24 x 18 x 12) and a
+half-plane grid (16 x 192 x 96: y-z planes of 18432 points, transformed
+as two half planes after a radix-2 y step in the x-line passes), a ragged
+one-plane grid (24 x 18 x 12) and a
 batch of 3 pairs; the pyramid runs three levels down from 32 x 192 x 96.
 """
 import ctypes

@@ -69,9 +69,12 @@ def test_fourier_solve(api, d, order):
     assert rel(host(w), ref) < 1e-5
 
 
-# y-z planes above 16384 points: pass B runs as three launches (rows,
-# columns, rows) instead of one plane per workgroup
-SPLIT_SHAPES = [(8, 144, 128), (12, 192, 96), (16, 96, 192)]
+# y-z planes above 16384 points.  Where half a plane fits one workgroup
+# (ny a multiple of 8) the x-line passes take a radix-2 step of the y
+# transform and pass B transforms each half plane in one workgroup (the first
+# three); otherwise pass B runs as three launches (rows, columns, rows; the
+# last: ny = 162)
+SPLIT_SHAPES = [(8, 144, 128), (12, 192, 96), (16, 96, 192), (8, 162, 108)]
 
 
 @pytest.mark.parametrize("d", SPLIT_SHAPES)
