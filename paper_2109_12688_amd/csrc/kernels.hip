@@ -62,8 +62,11 @@ static std::mutex g_rows_mu;
 static std::map<std::tuple<int, int, int>, int> g_rows;
 
 int xline_rows_default(const Geo& g) {
-  if (ysplit(g)) {  // two groups of 4 rows (runs of 32 bytes), else of 2
-    return (g.ny / 2) % 4 == 0 ? 8 : 4;
+  if (ysplit(g)) {  // two groups of 8 rows (runs of 64 bytes), else of 4, else of 2
+    // (measured at 192 x 192 x 128: 61.7-63.6 us for 16 rows, 63.9-66.7 for 8)
+    for (int rows = 16; rows >= 4; rows /= 2)
+      if ((g.ny / 2) % (rows / 2) == 0 && xline_rows_fit(g, rows, xline_threads_rows(g, rows))) return rows;
+    return 4;
   }
   const int cap = 1024 / g.nx < kXlMaxRows ? 1024 / g.nx : kXlMaxRows;
   for (int yb = cap & ~1; yb >= 2; yb -= 2)
