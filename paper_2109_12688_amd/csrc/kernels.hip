@@ -862,11 +862,11 @@ struct PlansRT {
   __device__ int ly() const { return py->L; }
   __device__ int lz() const { return pz->L; }
   template <bool INV>
-  __device__ void y_all(float2* line, const float2* tw, int tl) const {
+  __device__ __forceinline__ void y_all(float2* line, const float2* tw, int tl) const {
     for (int st = 0; st < py->nstages; ++st)
       team_stage_any<kTeamEpt, INV, 4>(line, tw, py->st[st], py->L, tl, 1);
   }
-  __device__ void z_fused(float2* line, const float2* tw, int tl, int es,
+  __device__ __forceinline__ void z_fused(float2* line, const float2* tw, int tl, int es,
                           const SpectralMult& mult) const {
     for (int st = 0; st + 1 < pz->nstages; ++st)
       team_stage_any<kTeamEpt, false, 0>(line, tw, pz->st[st], pz->L, tl, es);
