@@ -911,7 +911,7 @@ struct PlansCT {
 };
 
 // NY = NZ = 0: any size (run-time plans); otherwise the sizes are fixed.
-// DERIV: multiply by d/dlambda of the multiplier (generic kernel only).
+// DERIV: multiply by d/dlambda of the multiplier.
 // SUB: one of the two sub-planes (even or odd y frequencies) of a plane of a
 // half-plane size, bk.y = 2 c + s: the transform runs over ny / 2 (NY when
 // fixed), the plane is addressed and normalised with the full g.ny, and the
@@ -1352,18 +1352,28 @@ hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda,
   const XDivs xd = make_xdivs(g);
   const int rs = plane_row_stride(g);
   const TeamPlan tzi = reverse_team_plan(tz);
-#define NADMM_PASS_B(NY_, NZ_)                                                                 \
-  if (g.ny == NY_ && g.nz == NZ_) {                                                            \
-    hipLaunchKernelGGL((k_pass_b<NY_, NZ_>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X, \
-                       lambda, theta, order);                                                         \
-    return hipGetLastError();                                                                  \
+  // Plane sizes (ny, nz) with compile-time plans, each with the multiplier
+  // and with its derivative: every pair of 32, 64, 96 and 128, and the
+  // coarser levels of the three-level pyramid over 128 x 128 x 96 (64 x 48,
+  // 32 x 24) and over 192 x 192 x 128 (48 x 32).  The run-time-plan kernel
+  // serves every other size; at these sizes it takes 2.2-2.6x as long (14 us
+  // against 5.4 us for the 51 planes of 32 x 24, 13.9 against 6.3 us for the
+  // 99 planes of 64 x 48).
+#define NADMM_PASS_B(NY_, NZ_)                                                                      \
+  if (g.ny == NY_ && g.nz == NZ_) {                                                                 \
+    if (deriv)                                                                                      \
+      hipLaunchKernelGGL((k_pass_b<NY_, NZ_, true>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, \
+                         X, lambda, theta, order);                                                  \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_pass_b<NY_, NZ_>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X,    \
+                         lambda, theta, order);                                                     \
+    return hipGetLastError();                                                                       \
   }
-  if (!deriv) {  // the specialised kernels carry the multiplier only
   NADMM_PASS_B(32, 32) NADMM_PASS_B(32, 64) NADMM_PASS_B(32, 96) NADMM_PASS_B(32, 128)
   NADMM_PASS_B(64, 32) NADMM_PASS_B(64, 64) NADMM_PASS_B(64, 96) NADMM_PASS_B(64, 128)
   NADMM_PASS_B(96, 32) NADMM_PASS_B(96, 64) NADMM_PASS_B(96, 96) NADMM_PASS_B(96, 128)
   NADMM_PASS_B(128, 32) NADMM_PASS_B(128, 64) NADMM_PASS_B(128, 96) NADMM_PASS_B(128, 128)
-  }
+  NADMM_PASS_B(64, 48) NADMM_PASS_B(32, 24) NADMM_PASS_B(48, 32)
 #undef NADMM_PASS_B
   if (deriv)
     hipLaunchKernelGGL((k_pass_b<0, 0, true>), grid, block, lds, st, g, ty, tz, tzi, xd, rs, t, X,

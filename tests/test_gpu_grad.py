@@ -55,7 +55,7 @@ def pair(d, seed):
 
 
 @pytest.mark.parametrize("d,order,iters,ck", [((16, 12, 9), 2, 6, 2), ((24, 18, 16), 1, 7, 3),
-                                               ((12, 144, 128), 2, 4, 2)])
+                                               ((12, 144, 128), 2, 4, 2), ((16, 32, 24), 2, 5, 2)])
 def test_gradient_vs_oracle_adjoint(api, d, order, iters, ck):
     f, m = pair(d, 300)
     lam, theta = 0.02, 0.1

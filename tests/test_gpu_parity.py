@@ -15,8 +15,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 # shapes: several x-line tiles and y-z planes, odd nz, voxel counts that are
-# not multiples of the 256-thread elementwise blocks (ragged tails)
-SHAPES = [(8, 4, 4), (12, 6, 9), (24, 18, 9), (32, 32, 32), (48, 36, 27), (96, 64, 48)]
+# not multiples of the 256-thread elementwise blocks (ragged tails); planes of
+# 32 x 32, 64 x 48, 32 x 24 and 48 x 32 run compile-time-plan kernels, the
+# others the run-time-plan kernel
+SHAPES = [(8, 4, 4), (12, 6, 9), (24, 18, 9), (32, 32, 32), (48, 36, 27), (96, 64, 48), (16, 32, 24),
+          (24, 48, 32)]
 
 
 @pytest.fixture(scope="module")
