@@ -269,11 +269,14 @@ hipError_t spectral_apply(const Geo& g, const Plans& pl, const Tables& tb, const
 // added there in block order; the ADMM loop reads iteration k's check while
 // iteration k + 1 already runs (a stop at k then finalises from s^k, which
 // iteration k + 1 leaves in place), the warping loop waits for its check.
-constexpr int kSlotDoubles = 2 * kChangeBlocks;
+// The ADMM loop's sums come from the x-line pass that forms s^k (one pair of
+// sums per workgroup), so that its check reads no field again; the other
+// checks take a pass of their own over the two fields.
 struct StopRule {
   double tol_admm, tol_warp;
-  double* host;          // pinned host: 2 read-back slots of kSlotDoubles
+  double* host;          // pinned host: 2 read-back slots of 2 * slot_blocks doubles
   double* host_dev;      // the same memory as the device addresses it
+  int slot_blocks;       // partial sums per slot
   int nb[2];             // blocks of the check in each slot
   hipEvent_t ev[2];      // completion of each slot's partial sums
   double* admm_change;   // host, nullable: outer x (iters - 1) measured changes
@@ -292,7 +295,7 @@ struct StopRule {
 nadmm_status change_enqueue(const float* a, const float* b, size_t n, StopRule* stop, int slot,
                             hipStream_t st) {
   stop->nb[slot] = change_blocks(n);
-  HIP_TRY(launch_change_partials(a, b, n, stop->host_dev + (size_t)kSlotDoubles * slot, st));
+  HIP_TRY(launch_change_partials(a, b, n, stop->host_dev + (size_t)2 * stop->slot_blocks * slot, st));
   HIP_TRY(hipEventRecord(stop->ev[slot], st));
   return NADMM_OK;
 }
@@ -300,7 +303,7 @@ nadmm_status change_enqueue(const float* a, const float* b, size_t n, StopRule* 
 // Wait for slot `slot` and add its partials in block order: |a - b|^2 and |a|^2.
 nadmm_status change_sums(StopRule* stop, int slot, double& d, double& n) {
   HIP_TRY(hipEventSynchronize(stop->ev[slot]));
-  const double* part = stop->host + (size_t)kSlotDoubles * slot;
+  const double* part = stop->host + (size_t)2 * stop->slot_blocks * slot;
   d = 0.0;
   n = 0.0;
   for (int j = 0; j < stop->nb[slot]; ++j) {
@@ -314,7 +317,7 @@ nadmm_status change_sums(StopRule* stop, int slot, double& d, double& n) {
 // and whether |a - b| <= tol |a|.
 nadmm_status change_read(StopRule* stop, int slot, double tol, double& change, bool& below) {
   HIP_TRY(hipEventSynchronize(stop->ev[slot]));
-  const double* part = stop->host + (size_t)kSlotDoubles * slot;
+  const double* part = stop->host + (size_t)2 * stop->slot_blocks * slot;
   double d = 0.0, n = 0.0;
   for (int j = 0; j < stop->nb[slot]; ++j) {
     d += part[2 * j];
@@ -338,9 +341,13 @@ struct CheckHost {
       if (e) (void)hipEventDestroy(e);
     if (host) (void)hipHostFree(host);
   }
-  // Allocates the slots and events and points `stop` at them.
-  nadmm_status init(StopRule& stop) {
-    HIP_TRY(hipHostMalloc((void**)&host, 2 * kSlotDoubles * sizeof(double), hipHostMallocDefault));
+  // Allocates the slots (each for the larger of a separate check's blocks
+  // and the x-line pass's workgroups at geometry g) and the events, and
+  // points `stop` at them.
+  nadmm_status init(StopRule& stop, const Geo& g) {
+    const int xb = pass_c_blocks(g);
+    stop.slot_blocks = xb > kChangeBlocks ? xb : kChangeBlocks;
+    HIP_TRY(hipHostMalloc((void**)&host, 4 * (size_t)stop.slot_blocks * sizeof(double), hipHostMallocDefault));
     for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     stop.host = host;
     HIP_TRY(hipHostGetDevicePointer((void**)&stop.host_dev, host, 0));
@@ -378,9 +385,19 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     a.data_term = p->data_term;
     a.out = prev;  // s^k overwrites s^{k-2} voxel by voxel
     a.v_out = (k == p->iters - 1) ? v_last : nullptr;
+    // the threshold check of iteration k (not the last: it ends the loop
+    // anyway) from the pass that forms s^k, when it can hold the sums
+    const bool chk = stop && stop->tol_admm >= 0 && !J && batch == 1 && k + 1 < p->iters;
+    int chk_blocks = 0;
+    if (chk) a.chk_part = stop->host_dev + (size_t)2 * stop->slot_blocks * (k & 1);
     HIP_TRY(timed(KK_PASS_CA_ITER, st, [&] {
+      if (chk) return launch_pass_c_chk(g, pl.x, tb, a, st, stop->slot_blocks, &chk_blocks);
       return launch_pass_c(g, pl.x, tb, J ? kIterFwd : kIterFwdIw, a, st, batch);
     }));
+    if (chk_blocks > 0) {
+      stop->nb[k & 1] = chk_blocks;
+      HIP_TRY(hipEventRecord(stop->ev[k & 1], st));
+    }
     HIP_TRY(timed(KK_PASS_B, st, [&] {
       return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st, batch);
     }));
@@ -391,9 +408,10 @@ nadmm_status admm_iterations(const Geo& g, const Plans& pl, const Tables& tb,
     if (stop && stop->guard && p->iters >= 3 && (k == 1 || k == p->iters - 1))
       CHECK(change_enqueue(cur, prev, 3 * (size_t)g.V * batch, stop, k == 1 ? 0 : 1, st));
     if (stop && stop->tol_admm >= 0) {
-      // check iteration k (not the last: it ends the loop anyway), then read
-      // the check of iteration k - 1, enqueued one iteration ago
-      if (k + 1 < p->iters) CHECK(change_enqueue(cur, prev, 3 * (size_t)g.V, stop, k & 1, st));
+      // check iteration k (unless its x-line pass did), then read the check
+      // of iteration k - 1, enqueued one iteration ago
+      if (k + 1 < p->iters && chk_blocks == 0)
+        CHECK(change_enqueue(cur, prev, 3 * (size_t)g.V, stop, k & 1, st));
       if (k >= 2) {
         double ch;
         bool below;
@@ -746,7 +764,7 @@ nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, doubl
   CHECK(check_ptr(warped, "warped", true));
   StopRule stop{};
   CheckHost res{static_cast<hipStream_t>(stream)};
-  CHECK(res.init(stop));
+  CHECK(res.init(stop, geo(d)));
   stop.tol_admm = tol_admm;
   stop.tol_warp = tol_warp;
   stop.admm_change = admm_change;
@@ -780,7 +798,7 @@ nadmm_status nadmm_register_checked(nadmm_dims d, const nadmm_params* p, uint32_
   hipStream_t st = static_cast<hipStream_t>(stream);
   StopRule stop{};
   CheckHost res{st};
-  CHECK(res.init(stop));
+  CHECK(res.init(stop, geo(d)));
   stop.tol_admm = -1.0;
   stop.tol_warp = -1.0;
   stop.guard = (flags & NADMM_CHECK_DIVERGENCE) != 0;
@@ -1203,7 +1221,7 @@ nadmm_status nadmm_register_pyramid_threshold(nadmm_dims d, const nadmm_params* 
   for (int l = 0; outer_run && l < pyr->levels; ++l) outer_run[l] = 0;
   StopRule stop{};
   CheckHost res{static_cast<hipStream_t>(stream)};
-  CHECK(res.init(stop));
+  CHECK(res.init(stop, geo(d)));
   stop.tol_admm = tol_admm;
   stop.tol_warp = tol_warp;
   CHECK(pyramid_impl(d, p, pyr, fixed, moving, disp, warped, workspace, workspace_bytes, stream, &stop,

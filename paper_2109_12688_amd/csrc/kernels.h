@@ -114,8 +114,12 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 // kComposeBf16 is kCompose with the moving image stored as bfloat16.
 // kIterFwdIw is kIterFwd with J recomputed from the warped source iw (the
 // periodic central differences of k_grad_resid) instead of read.
+// kIterFwdIwChk is kIterFwdIw that also writes, for each workgroup, the FP64
+// sums of |s^k - s^{k-1}|^2 and |s^k|^2 over its voxels (the relative change
+// that threshold stopping of the ADMM loop compares, Sec. 4) to chk_part.
 enum PassCMode {
-  kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4, kIterFwdIw = 5
+  kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4, kIterFwdIw = 5,
+  kIterFwdIwChk = 6
 };
 
 struct PassCArgs {
@@ -139,6 +143,7 @@ struct PassCArgs {
   float* iw_out;       // kCompose: optional moving(x + u_new(x))
   float* vel_out;      // kCompose: optional velocity of this warping
   const float2* twy;   // y twiddles (the radix-2 y step of half-plane sizes)
+  double* chk_part;    // kIterFwdIwChk: (|s^k - s^{k-1}|^2, |s^k|^2) of workgroup b at [2 b], [2 b + 1]
 };
 
 hipError_t launch_fill(float* p, float value, size_t n, hipStream_t st);
@@ -178,6 +183,14 @@ hipError_t launch_pass_b(const Geo& g, const Tables& t, float2* X, float lambda,
                          int order, hipStream_t st, int batch = 1, bool deriv = false);
 hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
                          const PassCArgs& a, hipStream_t st, int batch = 1);
+// One pair's kIterFwdIwChk pass into a.chk_part, which holds cap_blocks
+// workgroups' sums: *blocks = the workgroups that wrote theirs.  When the
+// launch would need more than cap_blocks workgroups it runs kIterFwdIw
+// instead and sets *blocks = 0 (the caller then measures the change apart).
+hipError_t launch_pass_c_chk(const Geo& g, const FftPlan& px, const Tables& t, const PassCArgs& a,
+                             hipStream_t st, int cap_blocks, int* blocks);
+// Workgroups of one pair's x-line iteration pass at the current rows.
+int pass_c_blocks(const Geo& g);
 hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out, hipStream_t st);
 // Pyramid resampling: coarse (geometry gc) = 2x2x2 average of fine;
 // uf (geometry gf) = 2 uc((x - 1/2) / 2), periodic trilinear, per component.

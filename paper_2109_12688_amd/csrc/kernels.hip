@@ -1696,8 +1696,9 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
     run_of(idx, q4, xd, yy, x4);
     return bf + 2 * ((c * yb2 + (yy >> 1)) * ls + lpad<kXlPadsh>(4 * x4)) + (yy & 1);
   };
+  constexpr bool ITER = MODE == kIterFwd || MODE == kIterFwdIw || MODE == kIterFwdIwChk;
   float4 yv[MI][3];
-  if (MODE != kIterFwd && MODE != kIterFwdIw) {
+  if (!ITER) {
 #pragma unroll
     for (int it = 0; it < MI; ++it)
       if (threadIdx.x + it * nthr < nitems)
@@ -1714,7 +1715,10 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
       if (threadIdx.x + it * nthr < nitems)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
-  } else if (MODE == kIterFwd || MODE == kIterFwdIw) {
+  } else if (ITER) {
+    // change sums of the threshold check (FP64; the difference of two
+    // float32 values is exact there)
+    double chk_d = 0.0, chk_n = 0.0;
     // the runs one after the other (out may alias s2, so a run's loads stay
     // behind the previous run's stores; each run is read and written by the
     // same thread only); unrolled, at the same register count as a loop
@@ -1735,7 +1739,7 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
         s2v[c] = a.s2 ? ld4_at(a.s2 + c * g.V, go) : s1v[c];
         if constexpr (MODE == kIterFwd) jv[c] = ld4_at(a.J + c * g.V, go);
       }
-      if constexpr (MODE == kIterFwdIw) run_gradient(g, nx, a.iw, x0, y, z, jv);
+      if constexpr (MODE != kIterFwd) run_gradient(g, nx, a.iw, x0, y, z, jv);
       const float4 rv = ld4_at(a.r, go);
       float* slot[3];
 #pragma unroll
@@ -1762,6 +1766,16 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
           f4set(vo[c], e, v[c]);
         }
       }
+      if constexpr (MODE == kIterFwdIwChk) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double n = (double)f4get(so[c], e), dd = n - (double)f4get(s1v[c], e);
+            chk_d = fma(dd, dd, chk_d);
+            chk_n = fma(n, n, chk_n);
+          }
+      }
       const float gn = a.gamma_next;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1779,6 +1793,33 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
     __syncthreads();
     x_transform<NX, false>(buf, tw, px, xd, ls);
     store_half_spectrum<NX, YS>(g, xd, ls, buf, a.X, a.twy, by, z);
+    if constexpr (MODE == kIterFwdIwChk) {
+      // the workgroup's sums: each wavefront's by a butterfly of shuffles,
+      // then the wavefronts' in order (the same order on every run)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        chk_d += __shfl_xor(chk_d, off);
+        chk_n += __shfl_xor(chk_n, off);
+      }
+      __syncthreads();  // buf is free again
+      double* red = reinterpret_cast<double*>(lds);
+      const int wv = threadIdx.x >> 6;
+      if ((threadIdx.x & 63) == 0) {
+        red[2 * wv] = chk_d;
+        red[2 * wv + 1] = chk_n;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double d = 0.0, n = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+          d += red[2 * w];
+          n += red[2 * w + 1];
+        }
+        const size_t b = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+        a.chk_part[2 * b] = d;
+        a.chk_part[2 * b + 1] = n;
+      }
+    }
   } else if (MODE == kFinalWB) {
 #pragma unroll
     for (int it = 0; it < MI; ++it) {
@@ -1839,10 +1880,8 @@ __global__ void __launch_bounds__(kXlMaxThreads) k_pass_c(Geo g, FftPlan px, XDi
   pass_c_body<MODE, NX, YS>(g, px, xd, ls, twx, a, Blk::of_block());
 }
 
-hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
-                         const PassCArgs& a, hipStream_t st, int batch) {
-  // the composition pass has rows of its own (tuned separately)
-  const int yb = (mode == kCompose || mode == kComposeBf16) ? xline_rows_compose(g) : xline_rows(g);
+static hipError_t launch_pass_c_rows(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
+                                     const PassCArgs& a, hipStream_t st, int batch, int yb) {
   const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads_rows(g, yb));
   const size_t lds = pass_a_lds_rows(g, yb);
   const XDivs xd = make_xdivs_rows(g, yb);
@@ -1871,6 +1910,7 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
     case kOutY: NADMM_PASS_C_NX(kOutY); break;
     case kIterFwd: NADMM_PASS_C_NX(kIterFwd); break;
     case kIterFwdIw: NADMM_PASS_C_NX(kIterFwdIw); break;
+    case kIterFwdIwChk: NADMM_PASS_C_NX(kIterFwdIwChk); break;
     case kFinalWB: NADMM_PASS_C_NX(kFinalWB); break;
     case kComposeBf16: NADMM_PASS_C_NX(kComposeBf16); break;
     default: NADMM_PASS_C_NX(kCompose); break;
@@ -1878,6 +1918,22 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
 #undef NADMM_PASS_C_NX
 #undef NADMM_PASS_C
   return hipGetLastError();
+}
+
+hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassCMode mode,
+                         const PassCArgs& a, hipStream_t st, int batch) {
+  // the composition pass has rows of its own (tuned separately)
+  const int yb = (mode == kCompose || mode == kComposeBf16) ? xline_rows_compose(g) : xline_rows(g);
+  return launch_pass_c_rows(g, px, t, mode, a, st, batch, yb);
+}
+
+int pass_c_blocks(const Geo& g) { return g.ny / xline_rows(g) * g.nz; }
+
+hipError_t launch_pass_c_chk(const Geo& g, const FftPlan& px, const Tables& t, const PassCArgs& a,
+                             hipStream_t st, int cap_blocks, int* blocks) {
+  const int yb = xline_rows(g), nb = g.ny / yb * g.nz;  // the rows read once for both
+  *blocks = nb <= cap_blocks && a.chk_part ? nb : 0;
+  return launch_pass_c_rows(g, px, t, *blocks ? kIterFwdIwChk : kIterFwdIw, a, st, 1, yb);
 }
 
 // ---------------------------------------------------------------------------

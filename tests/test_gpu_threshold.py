@@ -76,6 +76,19 @@ def test_threshold_off_is_the_fixed_count_registration(api, blobs):
     assert torch.equal(g["disp"], ref["disp"]) and torch.equal(g["warped"], ref["warped"])
 
 
+def test_checks_never_met_is_the_fixed_count_registration(api, blobs):
+    """ADMM checks on with a threshold no change meets (0: the iterates never
+    repeat exactly): the x-line pass that also sums the change writes the same
+    fields, bit for bit, as the fixed-count registration's, and every check
+    measured a finite positive change."""
+    f, m = blobs
+    g = api.register_threshold(gpu(f), gpu(m), LAM, THETA, ORDER, 3, 6, 0.0, -1.0)
+    ref = api.register(gpu(f), gpu(m), LAM, THETA, ORDER, 3, 6)
+    assert g["iters_run"] == [6, 6, 6] and g["outer_run"] == 3
+    assert all(len(c) == 4 and all(0 < x < float("inf") for x in c) for c in g["admm_change"])
+    assert torch.equal(g["disp"], ref["disp"]) and torch.equal(g["warped"], ref["warped"])
+
+
 def test_threshold_first_checks(api, blobs):
     """A threshold above every change stops both loops at their first check:
     two warpings of two iterations."""
