@@ -189,3 +189,29 @@ def test_threshold_null_outputs_through_the_abi(api, blobs):
                                               ctypes.c_size_t(ws.numel()), api._stream())
     assert st == 0
     assert torch.equal(disp, ref["disp"])
+
+
+def test_pyramid_threshold_separate_checks_where_slots_are_short(api):
+    """The ADMM loop's checks come from the x-line pass while its workgroups'
+    sums fit the read-back slots (sized at the call's start for the finest
+    level, at least 1024 pairs), else from a pass of their own.  Rows pinned
+    to 16 at 128 x 128 x 96 (8 x 96 = 768 workgroups: slots of 1024) and to 2
+    at the middle level (32 x 48 = 1536 workgroups) put that level on the
+    separate pass: the same loop counts and the same fields, bit for bit."""
+    pair = synth.make_pair("phantom128x128x96")
+    w = synth.WORKLOADS["phantom128x128x96"]
+    f, m = gpu(pair.fixed), gpu(pair.moving)
+    fine, mid = tuple(f.shape), (48, 64, 64)
+    args = (w["lam"], w["theta"], w["order"], (4, 4, 3), (20, 20, 20), 0.05, 0.02)
+    ref = api.register_pyramid_threshold(f, m, *args)
+    try:
+        api.set_shapes(fine, 16)
+        api.set_shapes(mid, 2)
+        assert api.tuned_shapes(fine)["xline_rows"] == 16 and api.tuned_shapes(mid)["xline_rows"] == 2
+        g = api.register_pyramid_threshold(f, m, *args)
+    finally:
+        api.set_shapes(fine)
+        api.set_shapes(mid)
+    print(f"levels: {g['level_iters']}", flush=True)
+    assert g["level_iters"] == ref["level_iters"] and g["outer_run"] == ref["outer_run"]
+    assert torch.equal(g["disp"], ref["disp"]) and torch.equal(g["warped"], ref["warped"])
