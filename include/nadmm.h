@@ -161,8 +161,9 @@ nadmm_status nadmm_register(nadmm_dims d, const nadmm_params* p,
  * The outputs are written in every case (the registration runs to its fixed
  * counts).  Other arguments, workspace and errors as for nadmm_register (no
  * per-warping velocities).  SYNCHRONOUS: the guard reads two sums per
- * warping back (32 KB of pinned host memory and two events are allocated for
- * the call) and the call waits for the stream before returning. */
+ * warping back (pinned host memory as for nadmm_register_threshold and two
+ * events are allocated for the call) and the call waits for the stream
+ * before returning. */
 #define NADMM_CHECK_FINITE 1u
 #define NADMM_CHECK_DIVERGENCE 2u
 nadmm_status nadmm_register_checked(nadmm_dims d, const nadmm_params* p, uint32_t flags,
@@ -183,7 +184,7 @@ nadmm_status nadmm_register_checked(nadmm_dims d, const nadmm_params* p, uint32_
  * p->iters and p->outer remain the caps.  A negative tolerance switches its
  * check off (that loop runs to its cap); NaN is NADMM_ERR_INVALID_ARG.
  * Sums of squares are accumulated in FP64 from the float32 fields, in an
- * order that depends on the sizes only.
+ * order fixed by the sizes and the launch shapes (nadmm_tuned_shapes).
  *   iters_run    host out, p->outer int32 or NULL: ADMM iterations of each
  *                warping run (0 for warpings not run).
  *   outer_run    host out or NULL: warpings run.
@@ -194,13 +195,15 @@ nadmm_status nadmm_register_checked(nadmm_dims d, const nadmm_params* p, uint32_
  *                warping c at index c - 1 (NaN where not measured).
  * Other arguments, the workspace (nadmm_workspace_size bytes) and errors as
  * for nadmm_register (no initial displacement, no per-warping velocities).
- * SYNCHRONOUS: each check's per-block partial sums (at most 1024 pairs of
- * doubles) are written into pinned host memory and added there in block
- * order; an ADMM check is read while the next iteration already runs (on a
- * stop that iteration is discarded and the result is the one of the
- * stopping iteration), a warping check is waited for.  The call allocates
- * 32 KB of pinned host memory and two HIP events for its duration and
- * returns after the work is done. */
+ * SYNCHRONOUS: each check's partial sums are written into pinned host
+ * memory and added there in order (an ADMM check's by the iteration's own
+ * x-line pass, one pair of doubles per workgroup; a warping check's by a
+ * pass of its own, at most 1024 pairs); an ADMM check is read while the
+ * next iteration already runs (on a stop that iteration is discarded and
+ * the result is the one of the stopping iteration), a warping check is
+ * waited for.  The call allocates 32 KB of pinned host memory (32 bytes per
+ * x-line workgroup of the grid where that is more) and two HIP events for
+ * its duration and returns after the work is done. */
 nadmm_status nadmm_register_threshold(nadmm_dims d, const nadmm_params* p, double tol_admm,
                                       double tol_warp, const float* fixed, const float* moving,
                                       float* disp, float* warped, int32_t* iters_run,
@@ -296,8 +299,10 @@ nadmm_status nadmm_register_pyramid(nadmm_dims d, const nadmm_params* p, const n
  *              the ADMM iterations run (0 for warpings not run).
  *   outer_run  host out or NULL: pyr->levels int32, warpings run per level.
  * Other arguments, workspace and errors as for nadmm_register_pyramid
- * (NaN tolerances: NADMM_ERR_INVALID_ARG).  Synchronous, and allocates 32
- * KB of pinned host memory and two events for its duration, as
+ * (NaN tolerances: NADMM_ERR_INVALID_ARG).  Synchronous, and allocates
+ * pinned host memory (sized for the finest level; a coarser level whose
+ * x-line pass has more workgroups than that takes its ADMM checks from a
+ * pass of their own) and two events for its duration, as
  * nadmm_register_threshold does. */
 nadmm_status nadmm_register_pyramid_threshold(nadmm_dims d, const nadmm_params* p,
                                               const nadmm_pyramid* pyr, double tol_admm,
