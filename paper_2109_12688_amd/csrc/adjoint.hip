@@ -33,27 +33,6 @@ __device__ __forceinline__ void store3(float* p, int V, int i, const float v[3])
 
 }  // namespace
 
-// s_out = D(2y - t) + t - y with t = s1 + gamma (s1 - s2) (s2 may be null).
-__global__ void k_step_fwd(Geo g, const float* __restrict__ J, const float* __restrict__ r,
-                           const float* __restrict__ s1, const float* __restrict__ s2, float gamma,
-                           const float* __restrict__ y, float* __restrict__ s_out, float theta) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.V) return;
-  float j[3], a[3], v[3], t[3], yy[3];
-  load3(J, g.V, i, j);
-  load3(y, g.V, i, yy);
-  load3(s1, g.V, i, t);
-  if (s2) {
-    float p[3];
-    load3(s2, g.V, i, p);
-    for (int c = 0; c < 3; ++c) t[c] = fmaf(gamma, t[c] - p[c], t[c]);
-  }
-  for (int c = 0; c < 3; ++c) a[c] = 2.0f * yy[c] - t[c];
-  data_step(a, j, r[i], theta, 0.0f, 2, v);
-  for (int c = 0; c < 3; ++c) v[c] = v[c] + (t[c] - yy[c]);
-  store3(s_out, g.V, i, v);
-}
-
 // The adjoint of one step at a = 2y - t (t from s1, s2, gamma), or of the
 // initial data step at a = 0 when y is null.  Writes gy = 2 ga - g and
 // gt = g - ga (when the outputs are non-null) and accumulates gJ, gr.
@@ -202,14 +181,6 @@ __global__ void k_dot_final(const double* __restrict__ partial, int nparts, doub
 
 static dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-hipError_t launch_step_fwd(const Geo& g, const float* J, const float* r, const float* s1,
-                           const float* s2, float gamma, const float* y, float* s_out, float theta,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_step_fwd, grid1(g.V), dim3(256), 0, st, g, J, r, s1, s2, gamma, y, s_out,
-                     theta);
-  return hipGetLastError();
-}
-
 hipError_t launch_adj_step(const Geo& g, const float* gs, const float* s1, const float* s2,
                            float gamma, const float* y, const float* J, const float* r,
                            float theta, float* gy, float* gt, float* gJ, float* gr,
@@ -240,6 +211,12 @@ hipError_t launch_grad_transpose(const Geo& g, const float* gJ, const float* gr,
 }
 
 size_t dot_partials() { return kDotBlocks; }
+
+hipError_t launch_dot_final(const double* partial, int nparts, double scale, bool accumulate, double* out,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, partial, nparts, scale, accumulate ? 1 : 0, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_dot(size_t n, const float* a, const float* b, double scale, bool accumulate,
                       double* partial, double* out, hipStream_t st) {

@@ -545,6 +545,7 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
 // buffer), the adjoint ring and temporaries, all float32 vector fields.
 struct GradLayout {
   int nseg, nbuf;
+  size_t nparts;
   size_t J, r, gr, resid, X, tab, part, f3[64];
   int nf3;
   size_t total;
@@ -568,7 +569,11 @@ GradLayout grad_layout(const nadmm_dims& d, int iters, int c) {
   L.resid = o; o += f1;
   L.X = o; o += align256((size_t)3 * (d.nx / 2 + 1) * d.ny * d.nz * 2 * sizeof(float));
   L.tab = o; o += align256(tables_bytes(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}));
-  L.part = o; o += align256(dot_partials() * sizeof(double));
+  // dot partials: the dot pass's blocks, or the x-line pass's workgroups
+  // at any rows (the d/dlambda terms' sums)
+  const size_t xb = (size_t)pass_c_blocks_max(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz});
+  L.nparts = xb > dot_partials() ? xb : dot_partials();
+  L.part = o; o += align256(L.nparts * sizeof(double));
   for (int i = 0; i < L.nf3; ++i) {
     L.f3[i] = o;
     o += f3;
@@ -1297,15 +1302,37 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
     if ((k + 1) % c == 0 && (k + 1) / c < nck && k + 1 > 0) return ck_prev[(k + 1) / c];
     return buf[k % 2];
   };
+  // s^k for k = k0 .. k1 from the states before them (state(k) the slot of
+  // s^k): the registration's fused iteration with J read, i.e. one solve
+  // started on t^{k0}, then per step the x-line pass that forms s^k from
+  // S t^k and transforms the next input along x, and pass B
+  auto fwd_steps = [&](int k0, int k1, auto state) -> hipError_t {
+    hipError_t e = spectral_ab(g, pl, tb, p, state(k0 - 1), k0 >= 2 ? state(k0 - 2) : nullptr,
+                               (float)gam[k0 - 1], X, st);
+    for (int k = k0; k <= k1 && e == hipSuccess; ++k) {
+      PassCArgs a{};
+      a.X = X;
+      a.s1 = state(k - 1);
+      a.s2 = k >= 2 ? state(k - 2) : nullptr;
+      a.gamma = (float)gam[k - 1];
+      a.gamma_next = k < k1 ? (float)gam[k] : 0.0f;
+      a.J = J;
+      a.r = r;
+      a.theta = theta;
+      a.eps = (float)p->eps;
+      a.data_term = 2;
+      a.out = state(k);
+      e = timed(KK_PASS_CA_ITER, st, [&] { return launch_pass_c(g, pl.x, tb, kIterFwd, a, st); });
+      if (e == hipSuccess && k < k1)
+        e = timed(KK_PASS_B, st, [&] {
+          return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
+        });
+    }
+    return e;
+  };
   // u = 0: the warped source is the moving image itself
   HIP_TRY(launch_grad_resid(g, moving, fixed, J, r, fwd_slot(0), theta, (float)p->eps, 2, st));
-  for (int k = 1; k < K; ++k) {
-    const float* s1 = fwd_slot(k - 1);
-    const float* s2 = k >= 2 ? fwd_slot(k - 2) : nullptr;
-    const float gk = (float)gam[k - 1];
-    HIP_TRY(spectral_apply(g, pl, tb, p, s1, s2, gk, X, y, st));
-    HIP_TRY(launch_step_fwd(g, J, r, s1, s2, gk, y, fwd_slot(k), theta, st));
-  }
+  if (K >= 2) HIP_TRY(fwd_steps(1, K - 1, [&](int k) -> float* { return k < 0 ? nullptr : fwd_slot(k); }));
   float* s_last = fwd_slot(K - 1);
   HIP_TRY(spectral_apply(g, pl, tb, p, s_last, nullptr, 0.0f, X, w, st));
   if (!grads) {  // the loss alone: the same warp and residual as the adjoint kernel's
@@ -1319,9 +1346,23 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
   HIP_TRY(launch_fill(d_moving, 0.0f, V, st));
   HIP_TRY(launch_warp_adjoint(g, moving, fixed, w, resid, d_moving, gw, st));
   HIP_TRY(launch_dot(V, resid, resid, 1.0, false, part, loss, st));
+  // <o, (dS/dlambda) t> with t = s1 + gamma (s1 - s2), set or added into
+  // *d_lambda: the x-line pass of the solve sums its products with o per
+  // workgroup (the partials hold the most workgroups any rows give)
+  auto dot_deriv = [&](const float* s1, const float* s2, float gamma, const float* o, bool add) -> hipError_t {
+    hipError_t e = spectral_ab(g, pl, tb, p, s1, s2, gamma, X, st, 1, true);
+    if (e != hipSuccess) return e;
+    PassCArgs a{};
+    a.X = X;
+    a.s1 = o;
+    a.chk_part = part;
+    int nb = 0;
+    e = timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c_dot(g, pl.x, tb, a, st, (int)L.nparts, &nb); });
+    if (e != hipSuccess) return e;
+    return launch_dot_final(part, nb, 1.0, add, d_lambda, st);
+  };
   // w = S s^{K-1}: dL/dlambda gets <gw, (dS/dlambda) s^{K-1}>, dL/ds^{K-1} = S gw
-  HIP_TRY(spectral_apply(g, pl, tb, p, s_last, nullptr, 0.0f, X, tmp, st, true));
-  HIP_TRY(launch_dot(3 * V, gw, tmp, 1.0, false, part, d_lambda, st));
+  HIP_TRY(dot_deriv(s_last, nullptr, 0.0f, gw, false));
   for (int i = 0; i < 3; ++i) HIP_TRY(launch_fill(ring[i], 0.0f, 3 * V, st));
   HIP_TRY(spectral_apply(g, pl, tb, p, gw, nullptr, 0.0f, X, ring[(K - 1) % 3], st));
   HIP_TRY(launch_fill(gJ, 0.0f, 3 * V, st));
@@ -1336,11 +1377,7 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
       if (k == b - 1) return c == 1 ? ck_cur[j - 1] : ck_prev[j];  // c = 1 keeps every state
       return buf[k - b - 1];
     };
-    for (int k = b + 1; k <= kmax - 1; ++k) {  // recompute the segment's states
-      const float gk = (float)gam[k - 1];
-      HIP_TRY(spectral_apply(g, pl, tb, p, state(k - 1), state(k - 2), gk, X, y, st));
-      HIP_TRY(launch_step_fwd(g, J, r, state(k - 1), state(k - 2), gk, y, state(k), theta, st));
-    }
+    if (b + 1 <= kmax - 1) HIP_TRY(fwd_steps(b + 1, kmax - 1, state));  // recompute the segment's states
     for (int k = kmax; k > b; --k) {
       const float* s1 = state(k - 1);
       const float* s2 = k >= 2 ? state(k - 2) : nullptr;
@@ -1351,8 +1388,7 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
       HIP_TRY(spectral_apply(g, pl, tb, p, gy, nullptr, 0.0f, X, tmp, st));
       HIP_TRY(launch_adj_combine(3 * V, gt, tmp, gk, ring[(k - 1) % 3],
                                  k >= 2 ? ring[(k - 2) % 3] : nullptr, st));
-      HIP_TRY(spectral_apply(g, pl, tb, p, s1, s2, gk, X, tmp, st, true));
-      HIP_TRY(launch_dot(3 * V, gy, tmp, 1.0, true, part, d_lambda, st));
+      HIP_TRY(dot_deriv(s1, s2, gk, gy, true));
       HIP_TRY(launch_fill(gk_, 0.0f, 3 * V, st));  // becomes the adjoint of s^{k-3}
     }
   }

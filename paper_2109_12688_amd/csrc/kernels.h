@@ -117,9 +117,12 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 // kIterFwdIwChk is kIterFwdIw that also writes, for each workgroup, the FP64
 // sums of |s^k - s^{k-1}|^2 and |s^k|^2 over its voxels (the relative change
 // that threshold stopping of the ADMM loop compares, Sec. 4) to chk_part.
+// kDotY stores no y: each workgroup writes the FP64 sum of y . s1 over its
+// voxels (three components) to chk_part (a dot product with the output of
+// the solve, as the gradient's d/dlambda terms take it).
 enum PassCMode {
   kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4, kIterFwdIw = 5,
-  kIterFwdIwChk = 6
+  kIterFwdIwChk = 6, kDotY = 7
 };
 
 struct PassCArgs {
@@ -143,7 +146,8 @@ struct PassCArgs {
   float* iw_out;       // kCompose: optional moving(x + u_new(x))
   float* vel_out;      // kCompose: optional velocity of this warping
   const float2* twy;   // y twiddles (the radix-2 y step of half-plane sizes)
-  double* chk_part;    // kIterFwdIwChk: (|s^k - s^{k-1}|^2, |s^k|^2) of workgroup b at [2 b], [2 b + 1]
+  double* chk_part;    // kIterFwdIwChk: (|s^k - s^{k-1}|^2, |s^k|^2) of workgroup b at [2 b], [2 b + 1];
+                       // kDotY: y . s1 of workgroup b at [b]
 };
 
 hipError_t launch_fill(float* p, float value, size_t n, hipStream_t st);
@@ -189,8 +193,15 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
 // instead and sets *blocks = 0 (the caller then measures the change apart).
 hipError_t launch_pass_c_chk(const Geo& g, const FftPlan& px, const Tables& t, const PassCArgs& a,
                              hipStream_t st, int cap_blocks, int* blocks);
-// Workgroups of one pair's x-line iteration pass at the current rows.
+// Workgroups of one pair's x-line iteration pass at the current rows, and
+// the most that any rows give.
 int pass_c_blocks(const Geo& g);
+int pass_c_blocks_max(const Geo& g);
+// One pair's kDotY pass (a.s1 the other operand, a.chk_part holding
+// cap_blocks doubles): *blocks = the workgroups that wrote their sums, or
+// hipErrorInvalidValue (nothing launched) when more would be needed.
+hipError_t launch_pass_c_dot(const Geo& g, const FftPlan& px, const Tables& t, const PassCArgs& a,
+                             hipStream_t st, int cap_blocks, int* blocks);
 hipError_t launch_compose(const Geo& g, const float* u, const float* v, float* out, hipStream_t st);
 // Pyramid resampling: coarse (geometry gc) = 2x2x2 average of fine;
 // uf (geometry gf) = 2 uc((x - 1/2) / 2), periodic trilinear, per component.
@@ -199,9 +210,6 @@ hipError_t launch_upsample2_disp(const Geo& gf, const float* uc, float* uf, hipS
 
 // Differentiated warping (adjoint.hip).  Fields are float32 vector fields
 // (3V) unless noted; r, gr, resid, d_img are scalar volumes.
-hipError_t launch_step_fwd(const Geo& g, const float* J, const float* r, const float* s1,
-                           const float* s2, float gamma, const float* y, float* s_out, float theta,
-                           hipStream_t st);
 hipError_t launch_adj_step(const Geo& g, const float* gs, const float* s1, const float* s2,
                            float gamma, const float* y, const float* J, const float* r,
                            float theta, float* gy, float* gt, float* gJ, float* gr,
@@ -215,6 +223,10 @@ hipError_t launch_grad_transpose(const Geo& g, const float* gJ, const float* gr,
 // *out (device double) = (accumulate ? *out : 0) + scale * sum a[i] b[i],
 // float64, fixed summation order; `partial` holds dot_partials() doubles.
 size_t dot_partials();
+// *out = (accumulate ? *out : 0) + scale * the sum of partial[0 .. nparts),
+// added in one block in an order fixed by nparts.
+hipError_t launch_dot_final(const double* partial, int nparts, double scale, bool accumulate, double* out,
+                            hipStream_t st);
 hipError_t launch_dot(size_t n, const float* a, const float* b, double scale, bool accumulate,
                       double* partial, double* out, hipStream_t st);
 // Blocks of the first Jacobian launch; `partial` holds 4 doubles per block

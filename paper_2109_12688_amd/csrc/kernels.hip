@@ -1715,6 +1715,33 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
       if (threadIdx.x + it * nthr < nitems)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
+  } else if (MODE == kDotY) {
+    // products of two float32 values are exact in FP64
+    double acc = 0.0;
+#pragma unroll
+    for (int it = 0; it < MI; ++it)
+      if (threadIdx.x + it * nthr < nitems)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float4 o = ld4(a.s1 + c * g.V + gi[it]), y4 = yv[it][c];
+          acc = fma((double)y4.x, (double)o.x, acc);
+          acc = fma((double)y4.y, (double)o.y, acc);
+          acc = fma((double)y4.z, (double)o.z, acc);
+          acc = fma((double)y4.w, (double)o.w, acc);
+        }
+    // each wavefront's sum by a butterfly of shuffles, then the wavefronts'
+    // in order (the same order on every run)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    double* red = reinterpret_cast<double*>(lds);
+    __syncthreads();  // every thread has read its y from buf
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
+      a.chk_part[blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z)] = sum;
+    }
   } else if (ITER) {
     // change sums of the threshold check (FP64; the difference of two
     // float32 values is exact there)
@@ -1911,6 +1938,7 @@ static hipError_t launch_pass_c_rows(const Geo& g, const FftPlan& px, const Tabl
     case kIterFwd: NADMM_PASS_C_NX(kIterFwd); break;
     case kIterFwdIw: NADMM_PASS_C_NX(kIterFwdIw); break;
     case kIterFwdIwChk: NADMM_PASS_C_NX(kIterFwdIwChk); break;
+    case kDotY: NADMM_PASS_C_NX(kDotY); break;
     case kFinalWB: NADMM_PASS_C_NX(kFinalWB); break;
     case kComposeBf16: NADMM_PASS_C_NX(kComposeBf16); break;
     default: NADMM_PASS_C_NX(kCompose); break;
@@ -1928,6 +1956,16 @@ hipError_t launch_pass_c(const Geo& g, const FftPlan& px, const Tables& t, PassC
 }
 
 int pass_c_blocks(const Geo& g) { return g.ny / xline_rows(g) * g.nz; }
+int pass_c_blocks_max(const Geo& g) { return g.ny / 2 * g.nz; }  // rows are even
+
+hipError_t launch_pass_c_dot(const Geo& g, const FftPlan& px, const Tables& t, const PassCArgs& a,
+                             hipStream_t st, int cap_blocks, int* blocks) {
+  const int yb = xline_rows(g), nb = g.ny / yb * g.nz;  // the rows read once for both
+  *blocks = 0;
+  if (nb > cap_blocks || !a.chk_part || !a.s1) return hipErrorInvalidValue;
+  *blocks = nb;
+  return launch_pass_c_rows(g, px, t, kDotY, a, st, 1, yb);
+}
 
 hipError_t launch_pass_c_chk(const Geo& g, const FftPlan& px, const Tables& t, const PassCArgs& a,
                              hipStream_t st, int cap_blocks, int* blocks) {
