@@ -79,17 +79,6 @@ __global__ void k_adj_step(Geo g, const float* __restrict__ gs, const float* __r
   gr[i] -= cj;
 }
 
-// gt = gt_pre + sgy;  g1 += (1 + gamma) gt;  g2 -= gamma gt  (g2 may be null).
-__global__ void k_adj_combine(int n, const float* __restrict__ gt_pre,
-                              const float* __restrict__ sgy, float gamma, float* __restrict__ g1,
-                              float* __restrict__ g2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gt = gt_pre[i] + sgy[i];
-  g1[i] = fmaf(1.0f + gamma, gt, g1[i]);
-  if (g2) g2[i] = fmaf(-gamma, gt, g2[i]);
-}
-
 // The final warp and its adjoint: resid = I1(x + w) - I0 (written), the
 // image adjoint 2 resid scattered with the trilinear weights into d_img
 // (vector-memory float atomics) and gw = 2 resid * d/dp I1(p) at p = x + w.
@@ -187,13 +176,6 @@ hipError_t launch_adj_step(const Geo& g, const float* gs, const float* s1, const
                            hipStream_t st) {
   hipLaunchKernelGGL(k_adj_step, grid1(g.V), dim3(256), 0, st, g, gs, s1, s2, gamma, y, J, r,
                      theta, gy, gt, gJ, gr);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_combine(size_t n, const float* gt_pre, const float* sgy, float gamma,
-                              float* g1, float* g2, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_combine, grid1(n), dim3(256), 0, st, (int)n, gt_pre, sgy, gamma, g1,
-                     g2);
   return hipGetLastError();
 }
 

@@ -1385,11 +1385,19 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
       float* gk_ = ring[k % 3];
       HIP_TRY(spectral_apply(g, pl, tb, p, s1, s2, gk, X, y, st));
       HIP_TRY(launch_adj_step(g, gk_, s1, s2, gk, y, J, r, theta, gy, gt, gJ, gr, st));
-      HIP_TRY(spectral_apply(g, pl, tb, p, gy, nullptr, 0.0f, X, tmp, st));
-      HIP_TRY(launch_adj_combine(3 * V, gt, tmp, gk, ring[(k - 1) % 3],
-                                 k >= 2 ? ring[(k - 2) % 3] : nullptr, st));
+      // gt + S gy into the adjoints of s^{k-1} and s^{k-2}, and gk_ (read by
+      // the step's adjoint above) cleared to become the adjoint of s^{k-3}:
+      // all in the inverse x pass of the solve
+      HIP_TRY(spectral_ab(g, pl, tb, p, gy, nullptr, 0.0f, X, st));
+      PassCArgs ac{};
+      ac.X = X;
+      ac.s1 = gt;
+      ac.gamma = gk;
+      ac.out = ring[(k - 1) % 3];
+      ac.b_out = k >= 2 ? ring[(k - 2) % 3] : nullptr;
+      ac.v_out = gk_;
+      HIP_TRY(timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c(g, pl.x, tb, kAdjY, ac, st); }));
       HIP_TRY(dot_deriv(s1, s2, gk, gy, true));
-      HIP_TRY(launch_fill(gk_, 0.0f, 3 * V, st));  // becomes the adjoint of s^{k-3}
     }
   }
   // s^0 = D(0; J, r)

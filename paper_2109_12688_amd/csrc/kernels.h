@@ -120,9 +120,12 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 // kDotY stores no y: each workgroup writes the FP64 sum of y . s1 over its
 // voxels (three components) to chk_part (a dot product with the output of
 // the solve, as the gradient's d/dlambda terms take it).
+// kAdjY (the gradient's reverse pass) stores no y: with gt = s1 + y it sets
+// out = out + (1 + gamma) gt, b_out = b_out - gamma gt (b_out nullable) and
+// v_out = 0 (nullable), per voxel and component.
 enum PassCMode {
   kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4, kIterFwdIw = 5,
-  kIterFwdIwChk = 6, kDotY = 7
+  kIterFwdIwChk = 6, kDotY = 7, kAdjY = 8
 };
 
 struct PassCArgs {
@@ -214,8 +217,6 @@ hipError_t launch_adj_step(const Geo& g, const float* gs, const float* s1, const
                            float gamma, const float* y, const float* J, const float* r,
                            float theta, float* gy, float* gt, float* gJ, float* gr,
                            hipStream_t st);
-hipError_t launch_adj_combine(size_t n, const float* gt_pre, const float* sgy, float gamma,
-                              float* g1, float* g2, hipStream_t st);
 hipError_t launch_warp_adjoint(const Geo& g, const float* img, const float* ref, const float* w,
                                float* resid, float* d_img, float* gw, hipStream_t st);
 hipError_t launch_grad_transpose(const Geo& g, const float* gJ, const float* gr, float* d_img,

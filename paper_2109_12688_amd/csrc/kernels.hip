@@ -1715,6 +1715,25 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
       if (threadIdx.x + it * nthr < nitems)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
+  } else if (MODE == kAdjY) {
+    const float g1w = 1.0f + a.gamma;
+#pragma unroll
+    for (int it = 0; it < MI; ++it)
+      if (threadIdx.x + it * nthr < nitems)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const size_t o = (size_t)c * g.V + gi[it];
+          const float4 y4 = yv[it][c], p4 = ld4(a.s1 + o), q1 = ld4(a.out + o);
+          const float4 gt = make_float4(p4.x + y4.x, p4.y + y4.y, p4.z + y4.z, p4.w + y4.w);
+          st4(a.out + o, make_float4(fmaf(g1w, gt.x, q1.x), fmaf(g1w, gt.y, q1.y), fmaf(g1w, gt.z, q1.z),
+                                     fmaf(g1w, gt.w, q1.w)));
+          if (a.b_out) {
+            const float4 q2 = ld4(a.b_out + o);
+            st4(a.b_out + o, make_float4(fmaf(-a.gamma, gt.x, q2.x), fmaf(-a.gamma, gt.y, q2.y),
+                                         fmaf(-a.gamma, gt.z, q2.z), fmaf(-a.gamma, gt.w, q2.w)));
+          }
+          if (a.v_out) st4(a.v_out + o, make_float4(0.f, 0.f, 0.f, 0.f));
+        }
   } else if (MODE == kDotY) {
     // products of two float32 values are exact in FP64
     double acc = 0.0;
@@ -1939,6 +1958,7 @@ static hipError_t launch_pass_c_rows(const Geo& g, const FftPlan& px, const Tabl
     case kIterFwdIw: NADMM_PASS_C_NX(kIterFwdIw); break;
     case kIterFwdIwChk: NADMM_PASS_C_NX(kIterFwdIwChk); break;
     case kDotY: NADMM_PASS_C_NX(kDotY); break;
+    case kAdjY: NADMM_PASS_C_NX(kAdjY); break;
     case kFinalWB: NADMM_PASS_C_NX(kFinalWB); break;
     case kComposeBf16: NADMM_PASS_C_NX(kComposeBf16); break;
     default: NADMM_PASS_C_NX(kCompose); break;
