@@ -546,7 +546,7 @@ nadmm_status register_impl(nadmm_dims d, const nadmm_params* p, const T* fixed, 
 struct GradLayout {
   int nseg, nbuf;
   size_t nparts;
-  size_t J, r, gr, resid, X, tab, part, f3[64];
+  size_t J, r, gr, resid, X, X2, tab, part, f3[64];
   int nf3;
   size_t total;
 };
@@ -560,14 +560,15 @@ GradLayout grad_layout(const nadmm_dims& d, int iters, int c) {
   L.nseg = grad_segments(iters, c);
   L.nbuf = c - 1 > 2 ? c - 1 : 2;
   // checkpoints (2 per segment), shared segment/rolling buffers, ring (3),
-  // y, gy, gt, tmp, w, gw, gJ
-  L.nf3 = 2 * (L.nseg > 0 ? L.nseg : 1) + L.nbuf + 3 + 7;
+  // gy, gt, tmp, w, gw, gJ
+  L.nf3 = 2 * (L.nseg > 0 ? L.nseg : 1) + L.nbuf + 3 + 6;
   size_t o = 0;
   L.J = o; o += f3;
   L.r = o; o += f1;
   L.gr = o; o += f1;
   L.resid = o; o += f1;
   L.X = o; o += align256((size_t)3 * (d.nx / 2 + 1) * d.ny * d.nz * 2 * sizeof(float));
+  L.X2 = o; o += align256((size_t)3 * (d.nx / 2 + 1) * d.ny * d.nz * 2 * sizeof(float));
   L.tab = o; o += align256(tables_bytes(Geo{d.nx, d.ny, d.nz, d.nx * d.ny * d.nz}));
   // dot partials: the dot pass's blocks, or the x-line pass's workgroups
   // at any rows (the d/dlambda terms' sums)
@@ -1273,6 +1274,7 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
   float* gr = at<float>(workspace, L.gr);
   float* resid = at<float>(workspace, L.resid);
   float2* X = at<float2>(workspace, L.X);
+  float2* X2 = at<float2>(workspace, L.X2);  // the spectrum of t kept for the d/dlambda solve
   double* part = at<double>(workspace, L.part);
   const Tables tb = tables_at(g, at<char>(workspace, L.tab));
   int f = 0;
@@ -1285,7 +1287,6 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
   }
   for (int i = 0; i < L.nbuf; ++i) buf[i] = field();
   float* ring[3] = {field(), field(), field()};
-  float* y = field();
   float* gy = field();
   float* gt = field();
   float* tmp = field();
@@ -1349,11 +1350,15 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
   // <o, (dS/dlambda) t> with t = s1 + gamma (s1 - s2), set or added into
   // *d_lambda: the x-line pass of the solve sums its products with o per
   // workgroup (the partials hold the most workgroups any rows give)
-  auto dot_deriv = [&](const float* s1, const float* s2, float gamma, const float* o, bool add) -> hipError_t {
-    hipError_t e = spectral_ab(g, pl, tb, p, s1, s2, gamma, X, st, 1, true);
+  // (Xt: the x transform of t is already there, else X takes it)
+  auto dot_deriv = [&](const float* s1, const float* s2, float gamma, const float* o, bool add,
+                       float2* Xt = nullptr) -> hipError_t {
+    hipError_t e = Xt ? timed(KK_PASS_B, st, [&] {
+      return launch_pass_b(g, tb, Xt, (float)p->lambda, (float)p->theta, p->order, st, 1, true);
+    }) : spectral_ab(g, pl, tb, p, s1, s2, gamma, X, st, 1, true);
     if (e != hipSuccess) return e;
     PassCArgs a{};
-    a.X = X;
+    a.X = Xt ? Xt : X;
     a.s1 = o;
     a.chk_part = part;
     int nb = 0;
@@ -1383,12 +1388,33 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
       const float* s2 = k >= 2 ? state(k - 2) : nullptr;
       const float gk = (float)gam[k - 1];
       float* gk_ = ring[k % 3];
-      HIP_TRY(spectral_apply(g, pl, tb, p, s1, s2, gk, X, y, st));
-      HIP_TRY(launch_adj_step(g, gk_, s1, s2, gk, y, J, r, theta, gy, gt, gJ, gr, st));
+      // the step's adjoint in the inverse x pass of y = S t, which also
+      // transforms gy along x for the next solve; the x transform of t is
+      // kept in X2 for the d/dlambda solve
+      HIP_TRY(timed(KK_PASS_A, st, [&] { return launch_pass_a(g, pl.x, tb, s1, s2, gk, X, st, 1, X2); }));
+      HIP_TRY(timed(KK_PASS_B, st, [&] {
+        return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
+      }));
+      PassCArgs as{};
+      as.X = X;
+      as.s1 = s1;
+      as.s2 = s2;
+      as.gamma = gk;
+      as.J = J;
+      as.r = r;
+      as.theta = theta;
+      as.gs = gk_;
+      as.gy = gy;
+      as.gt = gt;
+      as.gJ = gJ;
+      as.gr = gr;
+      HIP_TRY(timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c(g, pl.x, tb, kAdjStep, as, st); }));
+      HIP_TRY(timed(KK_PASS_B, st, [&] {
+        return launch_pass_b(g, tb, X, (float)p->lambda, (float)p->theta, p->order, st);
+      }));
       // gt + S gy into the adjoints of s^{k-1} and s^{k-2}, and gk_ (read by
       // the step's adjoint above) cleared to become the adjoint of s^{k-3}:
       // all in the inverse x pass of the solve
-      HIP_TRY(spectral_ab(g, pl, tb, p, gy, nullptr, 0.0f, X, st));
       PassCArgs ac{};
       ac.X = X;
       ac.s1 = gt;
@@ -1397,7 +1423,7 @@ nadmm_status nadmm_ssd_grad(nadmm_dims d, const nadmm_params* p, int32_t checkpo
       ac.b_out = k >= 2 ? ring[(k - 2) % 3] : nullptr;
       ac.v_out = gk_;
       HIP_TRY(timed(KK_PASS_C_OUT, st, [&] { return launch_pass_c(g, pl.x, tb, kAdjY, ac, st); }));
-      HIP_TRY(dot_deriv(s1, s2, gk, gy, true));
+      HIP_TRY(dot_deriv(s1, s2, gk, gy, true, X2));
     }
   }
   // s^0 = D(0; J, r)

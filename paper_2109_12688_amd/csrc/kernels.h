@@ -123,9 +123,14 @@ hipError_t launch_tables(const Geo& g, const Tables& t, hipStream_t st);
 // kAdjY (the gradient's reverse pass) stores no y: with gt = s1 + y it sets
 // out = out + (1 + gamma) gt, b_out = b_out - gamma gt (b_out nullable) and
 // v_out = 0 (nullable), per voxel and component.
+// kAdjStep (the gradient's reverse pass) is the adjoint of one forward step
+// at y = S t (t = s1 + gamma (s1 - s2), s2 nullable; J, r, theta the data
+// term): from gs = dL/ds^k it stores gy = 2 ga - gs and gt = gs - ga
+// (ga = gs - (J.gs / q) J, q = theta + |J|^2), adds the data term's adjoints
+// into gJ and gr, and transforms gy along x into the spectrum it read.
 enum PassCMode {
   kOutY = 0, kIterFwd = 1, kFinalWB = 2, kCompose = 3, kComposeBf16 = 4, kIterFwdIw = 5,
-  kIterFwdIwChk = 6, kDotY = 7, kAdjY = 8
+  kIterFwdIwChk = 6, kDotY = 7, kAdjY = 8, kAdjStep = 9
 };
 
 struct PassCArgs {
@@ -149,6 +154,11 @@ struct PassCArgs {
   float* iw_out;       // kCompose: optional moving(x + u_new(x))
   float* vel_out;      // kCompose: optional velocity of this warping
   const float2* twy;   // y twiddles (the radix-2 y step of half-plane sizes)
+  const float* gs;     // kAdjStep: dL/ds^k
+  float* gy;           // kAdjStep outputs
+  float* gt;
+  float* gJ;           // kAdjStep: accumulated
+  float* gr;
   double* chk_part;    // kIterFwdIwChk: (|s^k - s^{k-1}|^2, |s^k|^2) of workgroup b at [2 b], [2 b + 1];
                        // kDotY: y . s1 of workgroup b at [b]
 };
@@ -175,8 +185,10 @@ hipError_t launch_grad_resid(const Geo& g, const float* iw, const uint16_t* ref,
                              hipStream_t st, int batch = 1);
 hipError_t launch_admm_init(const Geo& g, const float* J, const float* r, float* s0, float* v_out,
                             float theta, float eps, int data_term, hipStream_t st);
+// X2 (nullable): a second copy of the spectrum.
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
-                         const float* s2, float gamma, float2* X, hipStream_t st, int batch = 1);
+                         const float* s2, float gamma, float2* X, hipStream_t st, int batch = 1,
+                         float2* X2 = nullptr);
 // Pass A from the data term at the start of a warping: r = iw - ref and
 // s^0 (the data step from zero, J = grad iw) stored, s^0 transformed along x.
 hipError_t launch_pass_a0(const Geo& g, const FftPlan& px, const Tables& t, const float* iw,

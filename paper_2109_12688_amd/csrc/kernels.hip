@@ -756,12 +756,13 @@ __global__ void __launch_bounds__(kXlMaxThreads) k_pass_a(Geo g, FftPlan px, XDi
                                                 const float2* __restrict__ twy,
                                                 const float* __restrict__ s1,
                                                 const float* __restrict__ s2, float gamma,
-                                                float2* __restrict__ X) {
+                                                float2* __restrict__ X, float2* __restrict__ X2) {
   extern __shared__ float2 lds[];
   const int nx = NX ? NX : g.nx, q4 = nx / 4;
   s1 = at_pair(s1, 3 * (size_t)g.V, blockIdx.z);
   s2 = at_pair(s2, 3 * (size_t)g.V, blockIdx.z);
   X = at_pair(X, spectrum_elems(g), blockIdx.z);
+  X2 = at_pair(X2, spectrum_elems(g), blockIdx.z);
   const int yb = (int)xd.yb.d, yb2 = (int)xd.yb2.d;
   float2* tw = lds;
   float2* buf = lds + nx;
@@ -813,6 +814,7 @@ __global__ void __launch_bounds__(kXlMaxThreads) k_pass_a(Geo g, FftPlan px, XDi
   __syncthreads();
   x_transform<NX, false>(buf, tw, px, xd, ls);
   store_half_spectrum<NX, YS>(g, xd, ls, buf, X, twy, by, z);
+  if (X2) store_half_spectrum<NX, YS>(g, xd, ls, buf, X2, twy, by, z);  // a second copy
 }
 
 static size_t pass_a_lds_rows(const Geo& g, int yb) {
@@ -821,19 +823,19 @@ static size_t pass_a_lds_rows(const Geo& g, int yb) {
 static size_t pass_a_lds(const Geo& g) { return pass_a_lds_rows(g, xline_rows(g)); }
 
 hipError_t launch_pass_a(const Geo& g, const FftPlan& px, const Tables& t, const float* s1,
-                         const float* s2, float gamma, float2* X, hipStream_t st, int batch) {
+                         const float* s2, float gamma, float2* X, hipStream_t st, int batch, float2* X2) {
   const int yb = xline_rows(g);
   const dim3 grid(g.ny / yb, g.nz, batch), block(xline_threads(g));
   const size_t lds = pass_a_lds(g);
   const XDivs xd = make_xdivs(g);
   const int ls = xline_stride(g.nx);
 #define NADMM_PASS_A(N) \
-  hipLaunchKernelGGL(k_pass_a<N>, grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X)
+  hipLaunchKernelGGL(k_pass_a<N>, grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X, X2)
   if (ysplit(g)) {
     if (g.nx == 192)
-      hipLaunchKernelGGL((k_pass_a<192, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X);
+      hipLaunchKernelGGL((k_pass_a<192, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X, X2);
     else
-      hipLaunchKernelGGL((k_pass_a<0, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X);
+      hipLaunchKernelGGL((k_pass_a<0, true>), grid, block, lds, st, g, px, xd, ls, t.twx, t.twy, s1, s2, gamma, X, X2);
     return hipGetLastError();
   }
   switch (g.nx) {
@@ -1698,7 +1700,7 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
   };
   constexpr bool ITER = MODE == kIterFwd || MODE == kIterFwdIw || MODE == kIterFwdIwChk;
   float4 yv[MI][3];
-  if (!ITER) {
+  if (!ITER && MODE != kAdjStep) {
 #pragma unroll
     for (int it = 0; it < MI; ++it)
       if (threadIdx.x + it * nthr < nitems)
@@ -1715,6 +1717,72 @@ __device__ __forceinline__ void pass_c_body(const Geo& g, const FftPlan& px, con
       if (threadIdx.x + it * nthr < nitems)
 #pragma unroll
         for (int c = 0; c < 3; ++c) st4(a.out + c * g.V + gi[it], yv[it][c]);
+  } else if (MODE == kAdjStep) {
+    // the same arithmetic as the step adjoint of adjoint.hip, per run of 4
+    // voxels (each run read and written by one thread)
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      const int idx = threadIdx.x + it * nthr;
+      if (idx >= nitems) break;
+      int yy, x4;
+      run_of(idx, q4, xd, yy, x4);
+      const int x0 = 4 * x4;
+      const int y = tile_row(xd, by, yy);
+      const int go = (z * g.ny + y) * nx + x0;
+      float* slot[3];
+      float4 yr[3], s1v[3], s2v[3], jv[3], gv[3], gjv[3], gyo[3], gto[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        slot[c] = run_slot(it, c);
+        yr[c] = make_float4(slot[c][0], slot[c][2], slot[c][4], slot[c][6]);
+        s1v[c] = ld4_at(a.s1 + c * g.V, go);
+        s2v[c] = a.s2 ? ld4_at(a.s2 + c * g.V, go) : s1v[c];
+        jv[c] = ld4_at(a.J + c * g.V, go);
+        gv[c] = ld4_at(a.gs + c * g.V, go);
+        gjv[c] = ld4_at(a.gJ + c * g.V, go);
+      }
+      const float4 rv = ld4_at(a.r, go);
+      float4 grv = ld4_at(a.gr, go);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float t[3], av[3], j[3], gg[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float s = f4get(s1v[c], e);
+          t[c] = a.s2 ? fmaf(a.gamma, s - f4get(s2v[c], e), s) : s;
+          av[c] = 2.0f * f4get(yr[c], e) - t[c];
+          j[c] = f4get(jv[c], e);
+          gg[c] = f4get(gv[c], e);
+        }
+        const float q = a.theta + (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]);
+        const float f = (j[0] * av[0] + j[1] * av[1] + j[2] * av[2] + f4get(rv, e)) / q;
+        const float cj = (j[0] * gg[0] + j[1] * gg[1] + j[2] * gg[2]) / q;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float ga = gg[c] - cj * j[c];
+          const float dj = -f * gg[c] - cj * (av[c] - 2.0f * f * j[c]);
+          f4set(gyo[c], e, 2.0f * ga - gg[c]);
+          f4set(gto[c], e, gg[c] - ga);
+          f4set(gjv[c], e, f4get(gjv[c], e) + dj);
+        }
+        f4set(grv, e, f4get(grv, e) - cj);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        store_wt_at(a.gy + c * g.V, go, gyo[c]);
+        store_wt_at(a.gt + c * g.V, go, gto[c]);
+        store_wt_at(a.gJ + c * g.V, go, gjv[c]);
+        // gy is the next solve's input: written over the slots y came from
+        slot[c][0] = gyo[c].x;
+        slot[c][2] = gyo[c].y;
+        slot[c][4] = gyo[c].z;
+        slot[c][6] = gyo[c].w;
+      }
+      store_wt_at(a.gr, go, grv);
+    }
+    __syncthreads();
+    x_transform<NX, false>(buf, tw, px, xd, ls);
+    store_half_spectrum<NX, YS>(g, xd, ls, buf, a.X, a.twy, by, z);
   } else if (MODE == kAdjY) {
     const float g1w = 1.0f + a.gamma;
 #pragma unroll
@@ -1959,6 +2027,7 @@ static hipError_t launch_pass_c_rows(const Geo& g, const FftPlan& px, const Tabl
     case kIterFwdIwChk: NADMM_PASS_C_NX(kIterFwdIwChk); break;
     case kDotY: NADMM_PASS_C_NX(kDotY); break;
     case kAdjY: NADMM_PASS_C_NX(kAdjY); break;
+    case kAdjStep: NADMM_PASS_C_NX(kAdjStep); break;
     case kFinalWB: NADMM_PASS_C_NX(kFinalWB); break;
     case kComposeBf16: NADMM_PASS_C_NX(kComposeBf16); break;
     default: NADMM_PASS_C_NX(kCompose); break;
